@@ -1,0 +1,144 @@
+/*
+ * avm_oracle.h -- plain, slow, FP64 CPU oracle for microscopic
+ * electron-avalanche transport.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library is what the HIP implementation is
+ * checked against; only the test suite, the smoke check and the CPU-baseline
+ * leg of the benchmark may load it.  It shares no source, header, table or
+ * constant with the HIP implementation.
+ *
+ * What it computes (paper Sec. 2 and Fig. 2, the AvalancheMicroscopic outline:
+ * "position valid? -> find E field and add random time step -> collision? ->
+ * ionisation or attachment? -> store", repeated until every electron has a
+ * non-zero status; null-collision free flights after Skullerud, cited in
+ * Sec. 1): every electron of every avalanche is transported flight by flight
+ * through a gas described by an energy-binned rate table with linear
+ * interpolation between nodes, with a majorant rate Gamma >= nu(e) that turns
+ * the flight law into "exponential with rate Gamma, real with probability
+ * nu/Gamma".  Ionisation pushes a secondary electron; attachment and leaving
+ * the volume terminate one.  The readings taken where the paper is silent are
+ * listed in the design notes of the repository, and in the comments of
+ * avm_oracle.c next to the code they govern.
+ *
+ * Parity pins: every function here is pinned by a CPU test against a closed
+ * form, an invariant, brute force or an independent library (rocRAND's
+ * Philox for the generator).  Nothing here is "parity unpinned" except the
+ * physical correctness of the synthetic gas models, which are definitions.
+ */
+#ifndef AVM_ORACLE_H
+#define AVM_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { ORC_OK = 0, ORC_E_ARG = 1, ORC_E_NOMEM = 2 };
+
+/* channel kind / angular model / energy split / node value kind */
+enum { ORC_ELASTIC = 0, ORC_EXCITATION = 1, ORC_IONISATION = 2, ORC_ATTACHMENT = 3 };
+enum { ORC_ISOTROPIC = 0, ORC_SCREENED_RUTHERFORD = 1 };
+enum { ORC_SPLIT_UNIFORM = 0, ORC_SPLIT_OPAL_BEATY = 1 };
+enum { ORC_VALUES_SIGMA = 0, ORC_VALUES_RATE = 1 };
+
+/* electron status codes (non-zero = terminated) */
+enum {
+  ORC_ST_ACTIVE = 0, ORC_ST_LOW = 1, ORC_ST_HIGH = 2, ORC_ST_ATTACHED = 3,
+  ORC_ST_WIRE = 4, ORC_ST_TUBE = 5, ORC_ST_TIME = 6, ORC_ST_ABANDONED = 7,
+  ORC_ST_ERROR = 8
+};
+
+typedef struct {
+  int32_t kind, angular, split, values_kind;
+  double loss_eV, e_lo_eV, e_hi_eV, mass_ratio, split_w_eV, screening_eV;
+  const double* values; /* n_bins+1 node values: cm^2 or 1/ns */
+} orc_channel;
+
+typedef struct orc_gas orc_gas;
+typedef struct orc_field orc_field;
+
+/* Build the rate table: nu at the nodes, cumulative rates, per-bin maxima,
+ * band majorants (band_bins bins per band; 0 = a single band). */
+int orc_gas_create(double e_max_eV, int32_t n_bins, double density_cm3, int32_t n_ch,
+                   const orc_channel* ch, int32_t band_bins, orc_gas** out);
+void orc_gas_destroy(orc_gas*);
+double orc_gas_gamma(const orc_gas*);
+int32_t orc_gas_n_bands(const orc_gas*);
+/* Gamma_b and the upper edge (eV) of band b (edge = +inf for the last band). */
+int orc_gas_band(const orc_gas*, int32_t b, double* gamma_b, double* edge_eV);
+/* Replace Gamma (and every band majorant) by a larger value (tests only). */
+int orc_gas_set_gamma(orc_gas*, double gamma);
+/* Interpolated per-channel rates at energy e; returns 1 if e is above the
+ * table (rates then frozen at the last node). */
+int orc_gas_rates(const orc_gas*, double e_eV, double* nu_ch, double* nu_total);
+/* Copy of the cumulative table, node-major [(n_bins+1)][n_ch]. */
+int orc_gas_cumulative(const orc_gas*, double* out);
+int32_t orc_gas_band_of(const orc_gas*, double e_eV);
+
+/* Slab z_lo <= z < z_hi with one uniform field vector per avalanche
+ * (n_E == 1: the same field for every avalanche); B must be zero or along z. */
+int orc_field_slab(double z_lo, double z_hi, uint32_t n_E, const double* E_vcm,
+                   const double B_T[3], orc_field** out);
+/* Coaxial wire (radius a) and tube (radius b) with a polar map of (E_r, E_phi)
+ * float32 [n_r][n_phi] at r_i = a (b/a)^(i/(n_r-1)), phi_j = 2 pi j / n_phi. */
+int orc_field_polar(double a, double b, int32_t n_r, int32_t n_phi, const float* E_r,
+                    const float* E_phi, const double B_T[3], orc_field** out);
+void orc_field_destroy(orc_field*);
+int orc_field_eval(const orc_field*, const double r[3], uint32_t aval, double E[3]);
+
+typedef struct {
+  double x, y, z, t, e, dx, dy, dz;
+  uint32_t aval, _pad;
+} orc_primary; /* 72 bytes */
+
+typedef struct {
+  double x0, y0, z0, t0, e0, x1, y1, z1, t1, e1;
+  uint64_t eid, parent;
+  uint32_t aval, status, n_real, n_ion, n_null, n_masked, n_band, n_overflow;
+} orc_endpoint; /* 128 bytes */
+
+typedef struct {
+  uint64_t seed;
+  int32_t banded;      /* 0: global majorant; 1: banded majorant (B = 0 only) */
+  int32_t fifo;        /* 0: LIFO stack per avalanche; 1: FIFO queue */
+  double t_max_ns;     /* +inf: no time limit */
+  uint32_t k_max;      /* flight index limit (<= 2^30-1) */
+  int32_t n_threads;   /* 0: all online cores */
+} orc_opts;
+
+typedef struct orc_result orc_result;
+
+/* Transport every primary whose index is listed in `sel` (NULL: all).  The
+ * primary with array index i gets the electron id 2^63 | ids[i] (ids NULL:
+ * ids[i] = i).  Endpoints are returned grouped by avalanche. */
+int orc_run(const orc_gas*, const orc_field*, const orc_primary* prim, const uint64_t* ids,
+            uint64_t n_prim, const orc_opts*, orc_result** out, int32_t* threads_used);
+uint64_t orc_result_count(const orc_result*);
+int orc_result_copy(const orc_result*, orc_endpoint* out);
+void orc_result_destroy(orc_result*);
+
+/* ---- single steps, exported for the pins ---- */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+double orc_u53(uint32_t w_hi, uint32_t w_lo);
+float orc_u24(uint32_t w);
+double orc_cos_screened_rutherford(double u, double e_eV, double screening_eV);
+double orc_split_energy(int32_t split, double u, double e_avail, double w_eV);
+void orc_rotate(const double d[3], double cos_t, double phi, double out[3]);
+void orc_elastic(double e_eV, double mass_ratio, double cos_chi, double* e_out, double* cos_lab);
+/* First exit time of z(s) = z0 + vz s + az s^2/2 from [z_lo, z_hi) within
+ * (0, T]; returns 0 (none), ORC_ST_LOW or ORC_ST_HIGH. */
+int orc_slab_exit(double z0, double vz, double az, double z_lo, double z_hi, double T,
+                  double* s_exit);
+/* Smallest s >= 0 with |v + a s|^2 = 2 k_a e_edge (-1 if none). */
+double orc_band_root(const double v[3], const double a[3], double e_edge);
+/* Free flight over time s in a field frozen at E, optional B. */
+void orc_propagate(const double r0[3], const double v0[3], const double E[3], const double B[3],
+                   double s, double r[3], double v[3]);
+double orc_k_a(void);
+double orc_k_b(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

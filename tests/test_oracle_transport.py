@@ -1,0 +1,258 @@
+"""Pins of the oracle's whole transport loop against closed forms,
+per-trajectory identities, invariants and order independence."""
+import math
+
+import numpy as np
+import pytest
+from scipy import stats
+
+from paper_2509_15377_amd import workloads as W
+
+UNBOUNDED = 1e3  # cm: a slab no electron reaches in these tests
+
+
+def _at(n, e=0.0, d=(0.0, 0.0, 1.0)):
+    p = W.primaries_at_rest(n)
+    p["e"] = e
+    p["dx"], p["dy"], p["dz"] = d
+    return p
+
+
+def _open_slab(E0, B=(0.0, 0.0, 0.0)):
+    f = W.slab(2 * UNBOUNDED, E0, B)
+    f.z_lo_cm = -UNBOUNDED
+    f.z_hi_cm = UNBOUNDED
+    return f
+
+
+def test_flight_law_is_exponential_in_gamma(oracle_mod):
+    """First flight time ~ Exp(Gamma); with a constant real rate nu0 < Gamma
+    the real collisions in [0, T] are Poisson(nu0 T), the nulls
+    Poisson((Gamma - nu0) T)."""
+    O = oracle_mod
+    nu0, gam = 1000.0, 4000.0
+    g = O.Gas(W.constant_rate_gas(nu0))
+    g.set_gamma(gam)
+    f = O.Field(_open_slab(0.0))
+    ep = O.run(g, f, _at(20000), seed=31, k_max=1)
+    assert (ep["status"] == 7).all()
+    tau = ep["t1"] - ep["t0"]
+    assert stats.kstest(tau, "expon", args=(0, 1 / gam)).pvalue > 1e-3
+    T = 0.01
+    ep = O.run(g, f, _at(20000), seed=32, t_max=T)
+    assert (ep["status"] == 6).all() and np.all(ep["t1"] == T)
+    for key, lam in (("n_real", nu0 * T), ("n_null", (gam - nu0) * T)):
+        x = ep[key].astype(float)
+        assert abs(x.mean() - lam) < 5 * math.sqrt(lam / x.size)
+        assert abs(x.var() - lam) < 0.1 * lam
+        kmax = int(lam * 3)
+        obs = np.bincount(np.minimum(x.astype(int), kmax), minlength=kmax + 1)
+        pk = stats.poisson.pmf(np.arange(kmax + 1), lam)
+        pk[-1] = stats.poisson.sf(kmax - 1, lam)
+        keep = pk * x.size > 5
+        exp = pk[keep] * x.size
+        o = obs[keep]
+        assert stats.chisquare(o, exp * o.sum() / exp.sum()).pvalue > 1e-3
+
+
+def test_channel_frequencies_at_fixed_energy(oracle_mod):
+    """One decision at 5 eV in zero field: null / elastic / excitation /
+    ionisation / attachment / masked with probabilities nu_c / Gamma."""
+    O = oracle_mod
+    n_bins = 100
+    mk = lambda v: np.full(n_bins + 1, float(v))
+    chans = [
+        W.Channel(W.ELASTIC, mk(100), values_kind=W.VALUES_RATE),
+        W.Channel(W.EXCITATION, mk(200), values_kind=W.VALUES_RATE, loss_eV=1.0, e_lo_eV=1.0),
+        W.Channel(W.IONISATION, mk(300), values_kind=W.VALUES_RATE, loss_eV=2.0, e_lo_eV=2.0),
+        W.Channel(W.ATTACHMENT, mk(50), values_kind=W.VALUES_RATE, e_hi_eV=10.0),
+        W.Channel(W.EXCITATION, mk(150), values_kind=W.VALUES_RATE, loss_eV=7.0, e_lo_eV=7.0),
+    ]
+    g = O.Gas(W.Gas(100.0, n_bins, 2.5e19, chans))
+    g.set_gamma(1000.0)
+    f = O.Field(_open_slab(0.0))
+    n = 40000
+    ep = O.run(g, f, _at(n, e=5.0), seed=33, k_max=1)
+    prim = ep[ep["parent"] == 0]
+    assert prim.size == n
+    cats = np.array([
+        (prim["n_null"] == 1).sum(),
+        ((prim["n_real"] == 1) & (np.abs(prim["e1"] - 5.0) < 1e-9) & (prim["status"] != 3)).sum(),
+        ((prim["n_real"] == 1) & (np.abs(prim["e1"] - 4.0) < 1e-9)).sum(),
+        (prim["n_ion"] == 1).sum(),
+        (prim["status"] == 3).sum(),
+        (prim["n_masked"] == 1).sum(),
+    ])
+    assert cats.sum() == n
+    p = np.array([200, 100, 200, 300, 50, 150]) / 1000.0
+    assert stats.chisquare(cats, p * n).pvalue > 1e-3
+    # each ionisation of a primary pushed exactly one secondary
+    assert ((ep["parent"] >> 63) == 1).sum() == cats[3]
+
+
+def test_energy_gain_per_flight(oracle_mod):
+    """e_end - e_start = -E . (r_end - r_start) over a flight (null outcome),
+    and at a boundary exit, per trajectory."""
+    O = oracle_mod
+    gas = W.argon_like_gas()
+    rng = np.random.default_rng(34)
+    n = 4000
+    p = W.primaries_at_rest(n)
+    p["z"] = rng.uniform(0, 128e-4, n)
+    p["e"] = rng.uniform(0, 20, n)
+    d = rng.normal(size=(n, 3))
+    p["dx"], p["dy"], p["dz"] = d.T
+    E0 = 40e3
+    ep = O.run(gas, W.slab(128e-4, E0), p, seed=35, k_max=1)
+    sel = (ep["parent"] == 0) & (ep["n_real"] == 0)
+    assert sel.sum() > 100
+    gain = ep["e1"][sel] - ep["e0"][sel]
+    work = E0 * (ep["z1"][sel] - ep["z0"][sel])  # -E . dr with E = (0, 0, -E0)
+    assert np.allclose(gain, work, rtol=1e-9, atol=1e-9)
+    assert (ep["status"][sel] != 0).all()
+
+
+def test_langevin_constant_frequency_no_loss(oracle_mod):
+    """mu = 0, isotropic, constant nu: <z(t)> = (a/nu)[t - (1 - e^{-nu t})/nu]
+    and, per electron, e(t) = E0 z(t) (no energy loss).  With nu = 1e3/ns and
+    E = 1e4 V/cm the drift velocity a/nu is 0.017588 cm/ns."""
+    O = oracle_mod
+    nu, E0 = 1000.0, 1e4
+    a = O.k_a() * E0
+    assert a / nu == pytest.approx(0.017588, rel=1e-4)
+    g = O.Gas(W.constant_rate_gas(nu))
+    g.set_gamma(1500.0)  # nulls must not bias anything
+    f = O.Field(_open_slab(E0))
+    for T in (0.002, 0.01):
+        ep = O.run(g, f, _at(20000), seed=36, t_max=T)
+        z = ep["z1"]
+        want = (a / nu) * (T - (1 - math.exp(-nu * T)) / nu)
+        assert abs(z.mean() - want) < 5 * z.std() / math.sqrt(z.size)
+        assert np.allclose(ep["e1"], E0 * z, rtol=1e-9, atol=1e-12)
+
+
+def test_langevin_finite_mass_ratio(oracle_mod):
+    """mu > 0, isotropic, constant nu: momentum relaxes at kappa = nu/(1+mu),
+    energy at lambda = 2 mu nu/(1+mu)^2; v_d = (1+mu) a/nu and
+    <e(t)> = A(1-e^{-lambda t})/lambda - A(e^{-kappa t}-e^{-lambda t})/(lambda-kappa)
+    with A = E0 v_d."""
+    O = oracle_mod
+    nu, E0, mu = 1000.0, 1e4, 0.01
+    a = O.k_a() * E0
+    kap = nu / (1 + mu)
+    lam = 2 * mu * nu / (1 + mu) ** 2
+    vd = a / kap
+    A = E0 * vd
+    g = O.Gas(W.constant_rate_gas(nu, mass_ratio=mu))
+    f = O.Field(_open_slab(E0))
+    for T in (0.02, 0.1):
+        ep = O.run(g, f, _at(12000), seed=37, t_max=T)
+        e_want = A * (1 - math.exp(-lam * T)) / lam - A * (math.exp(-kap * T) - math.exp(-lam * T)) / (lam - kap)
+        z_want = vd * (T - (1 - math.exp(-kap * T)) / kap)
+        e, z = ep["e1"], ep["z1"]
+        assert abs(e.mean() - e_want) < 5 * e.std() / math.sqrt(e.size)
+        assert abs(z.mean() - z_want) < 5 * z.std() / math.sqrt(z.size)
+
+
+def test_avalanche_invariants(oracle_mod):
+    O = oracle_mod
+    wl = W.highgain(3)
+    g = O.Gas(wl.gas, band_bins=100)
+    ep = O.run(g, wl.field, wl.primaries, wl.seed, banded=True)
+    pa = O.per_avalanche(ep, wl.n_aval)
+    # gain bookkeeping: endpoints = primaries + ionisations, per avalanche
+    assert np.array_equal(pa["n_endpoints"], 1 + pa["n_ion"])
+    assert (ep["status"] != 0).all()
+    assert np.unique(ep["eid"]).size == ep.size
+    # every secondary's parent is an electron of the same avalanche
+    key = set(zip(ep["aval"].tolist(), ep["eid"].tolist()))
+    sec = ep[ep["parent"] != 0]
+    assert all((a, p) in key for a, p in zip(sec["aval"].tolist(), sec["parent"].tolist()))
+    # primaries carry 2^63 | index, secondaries a 63-bit id
+    assert ((ep["eid"][ep["parent"] == 0] >> 63) == 1).all()
+    assert ((sec["eid"] >> 63) == 0).all()
+    # Opal-Beaty: the secondary is the slower electron, e_s <= (e - I)/2
+    assert sec["e0"].max() <= (400.0 - 15.7) / 2
+    # a secondary starts where and when its parent ionised: inside the slab,
+    # between the parent's start and end times
+    par = {(a, e): (t0, t1) for a, e, t0, t1 in zip(ep["aval"].tolist(), ep["eid"].tolist(),
+                                                    ep["t0"].tolist(), ep["t1"].tolist())}
+    for a, p_, t0 in zip(sec["aval"][:2000].tolist(), sec["parent"][:2000].tolist(),
+                         sec["t0"][:2000].tolist()):
+        pt0, pt1 = par[(a, p_)]
+        assert pt0 <= t0 <= pt1
+    assert ((sec["z0"] >= 0) & (sec["z0"] < 128e-4)).all()
+    assert pa["n_att"].sum() > 0
+
+
+def test_order_thread_and_subset_independence(oracle_mod):
+    """LIFO and FIFO processing, any thread count, and any avalanche subset
+    give bit-identical endpoints keyed by (avalanche, electron id)."""
+    O = oracle_mod
+    wl = W.argon(24)
+    g = O.Gas(wl.gas, band_bins=100)
+    f = O.Field(wl.field)
+    a = O.run(g, f, wl.primaries, wl.seed, banded=True, fifo=False, threads=8)
+    b = O.run(g, f, wl.primaries, wl.seed, banded=True, fifo=True, threads=1)
+    assert a.tobytes() == b.tobytes()
+    idx = W.subset_primaries(wl.primaries, 5, 2)
+    c = O.run(g, f, wl.primaries[idx], wl.seed, banded=True, ids=idx)
+    assert c.tobytes() == a[(a["aval"] % 5) == 2].tobytes()
+    # a different seed gives a different avalanche
+    d = O.run(g, f, wl.primaries, wl.seed + 1, banded=True)
+    assert d.size != a.size or d.tobytes() != a.tobytes()
+
+
+@pytest.mark.slow
+def test_banded_equals_global_in_distribution(oracle_mod):
+    O = oracle_mod
+    wl = W.toy(800)
+    f = O.Field(wl.field)
+    glob = O.run(O.Gas(wl.gas), f, wl.primaries, 41)
+    band = O.run(O.Gas(wl.gas, band_bins=20), f, wl.primaries, 41, banded=True)
+    assert band["n_band"].sum() > 0 and glob["n_band"].sum() == 0
+    # nulls drop by an order of magnitude
+    assert band["n_null"].sum() * 5 < glob["n_null"].sum()
+    ga = np.bincount(glob["aval"], minlength=800)
+    gb = np.bincount(band["aval"], minlength=800)
+    assert stats.ks_2samp(ga, gb).pvalue > 1e-3
+    se = math.sqrt(ga.var() / ga.size + gb.var() / gb.size)
+    assert abs(ga.mean() - gb.mean()) < 4 * se
+    for key in ("t1", "e1", "x1"):
+        assert stats.ks_2samp(glob[key], band[key]).pvalue > 1e-3
+    rr = glob["n_real"].sum() / glob.size, band["n_real"].sum() / band.size
+    assert rr[0] == pytest.approx(rr[1], rel=0.03)
+
+
+def test_polar_map_field_and_wire_transport(oracle_mod):
+    O = oracle_mod
+    wl = W.wire(6)
+    fm = wl.field
+    f = O.Field(fm)
+    a, b = fm.a_cm, fm.b_cm
+    rng = np.random.default_rng(42)
+    for _ in range(200):
+        i = int(rng.integers(0, 512))
+        r = a * (b / a) ** (i / 511)
+        phi = rng.uniform(0, 2 * math.pi)
+        E = f.eval([r * math.cos(phi), r * math.sin(phi), 0.3])
+        want = 1500.0 / (r * math.log(b / a))
+        # at a radial node the bilinear map returns the stored float32 value
+        assert np.hypot(E[0], E[1]) == pytest.approx(float(np.float32(want)), rel=1e-9)
+        assert E[0] * math.cos(phi) + E[1] * math.sin(phi) > 0  # radially outward
+        assert E[2] == 0.0
+    # between nodes: linear in ln r
+    r1, r2 = a * (b / a) ** (100 / 511), a * (b / a) ** (101 / 511)
+    rm = math.sqrt(r1 * r2)
+    E = f.eval([rm, 0.0, 0.0])
+    assert E[0] == pytest.approx(0.5 * (float(np.float32(1500 / (r1 * math.log(b / a))))
+                                        + float(np.float32(1500 / (r2 * math.log(b / a))))), rel=1e-9)
+    ep = O.run(O.Gas(wl.gas), f, wl.primaries, wl.seed)
+    pa = O.per_avalanche(ep, wl.n_aval)
+    assert np.array_equal(pa["n_endpoints"], 1 + pa["n_ion"])
+    st = np.bincount(ep["status"], minlength=9)
+    assert st[4] > 0.9 * ep.size  # electrons end on the wire
+    rho = np.hypot(ep["x1"], ep["y1"])
+    assert np.allclose(rho[ep["status"] == 4], a, rtol=1e-12)
+    with pytest.raises(ValueError):
+        O.run(O.Gas(wl.gas, band_bins=100), f, wl.primaries, wl.seed, banded=True)
