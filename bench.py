@@ -1,0 +1,159 @@
+"""Benchmark: electron real collisions/s and secondaries/s of microscopic
+avalanche transport on one MI355X, on the argon-like gas at gain ~1e3
+(1000 avalanches of one primary electron each, 128 um gap, 40 kV/cm).
+
+One step = one complete avalanche simulation of the whole batch (every
+electron carried to termination, statistics reduced), primaries already
+resident in HBM.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# Algorithmic VALU work per event, in lane operations (the minimum the
+# method performs per flight / real collision / ionisation / endpoint; see the
+# design notes for the derivation).  Peak: 256 CUs x 4 SIMD16 x 2.4 GHz x 16
+# lanes = 3.93e13 lane-ops/s (FP64 FMA counted as one op).
+OPS_PER_FLIGHT = 150
+OPS_PER_REAL = 220
+OPS_PER_ION = 280
+PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="argon")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain-mode reference leg")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              f"(--gpus {args.gpus} requested)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2509_15377_amd import avm, workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    band_bins = 100
+    wl = W.WORKLOADS[args.workload](band_bins=band_bins)
+    dev = torch.device("cuda:0")
+    prim_dev = torch.from_numpy(wl.primaries.view(np.uint8).copy()).to(dev)
+    stream = torch.cuda.current_stream()
+    gas = avm.Gas(wl.gas, 0)
+    field = avm.Field(wl.field, 0)
+    capacity = 16_000_000
+
+    def make(mode, majorant, precision=avm.FP64):
+        return avm.Run(gas, field, prim_dev, wl.n_aval, seed=wl.seed, precision=precision,
+                       majorant=majorant, mode=mode, capacity=capacity, timeout_s=300.0,
+                       stream=stream)
+
+    run = make(avm.BATCHED, avm.BANDED)
+    for _ in range(args.warmup):
+        run.execute()
+        run.sync()
+    torch.cuda.synchronize()
+    kernel_ms = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        run.execute()
+        run.sync()
+        kernel_ms.append(run.timing()[0])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    c = run.counts()
+    flights = c["n_real"] + c["n_null"] + c["n_masked"] + c["n_band"]
+    ms_step = wall * 1e3 / args.steps
+    value = c["n_real"] / (ms_step * 1e-3)
+    k_ms = sum(kernel_ms) / len(kernel_ms)
+    ops = flights * OPS_PER_FLIGHT + c["n_real"] * OPS_PER_REAL + c["n_ion"] * OPS_PER_ION
+    achieved = ops / (k_ms * 1e-3)
+
+    paths = {"batched_fp64_banded": {"real_collisions_per_s": value,
+                                     "secondaries_per_s": c["n_ion"] / (ms_step * 1e-3),
+                                     "flights_per_s": flights / (ms_step * 1e-3),
+                                     "ms_per_step": ms_step, "kernel_ms": k_ms}}
+    if not args.no_plain:
+        # the paper's scheduling (one kernel per transport iteration, host
+        # reads the active count back) with the global majorant, one pass
+        pr = make(avm.PLAIN, avm.GLOBAL)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        pr.execute()
+        pr.sync()
+        tp = time.perf_counter() - t1
+        pc = pr.counts()
+        pk, it = pr.timing()
+        paths["plain_fp64_global"] = {"real_collisions_per_s": pc["n_real"] / tp,
+                                      "secondaries_per_s": pc["n_ion"] / tp,
+                                      "flights_per_s": (pc["n_real"] + pc["n_null"] + pc["n_masked"]) / tp,
+                                      "ms_per_step": tp * 1e3, "kernel_ms": pk, "iterations": it}
+        pr.close()
+
+    cpu = None
+    if not args.no_cpu:
+        from oracle import oracle as O
+        idx = W.subset_primaries(wl.primaries, 4)
+        og = O.Gas(wl.gas)
+        of = O.Field(wl.field)
+        t2 = time.perf_counter()
+        ep, threads = O.run(og, of, wl.primaries[idx], wl.seed, banded=True, ids=idx,
+                            return_threads=True)
+        tc = time.perf_counter() - t2
+        cpu = {"value": float(ep["n_real"].sum() / tc), "unit": "real collisions/s",
+               "cores": int(threads), "kind": "oracle",
+               "sample": f"avalanches with id % 4 == 0 ({idx.size} of {wl.n_aval}), "
+                         f"banded majorant, FP64, {tc:.1f} s",
+               "secondaries_per_s": float(ep["n_ion"].sum() / tc)}
+
+    line = {
+        "metric": "electron real collisions/s (secondaries/s alongside) at gain ~1e3",
+        "value": value,
+        "unit": "collisions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{wl.name}: {wl.description}", "avalanches": wl.n_aval,
+                   "electrons_per_step": c["n_endpoints"], "mean_gain": c["n_endpoints"] / wl.n_aval,
+                   "path": "batched persistent kernel, banded majorant (100 bins/band), FP64",
+                   "seed": wl.seed},
+        "secondaries_per_s": c["n_ion"] / (ms_step * 1e-3),
+        "flights_per_s": flights / (ms_step * 1e-3),
+        "null_fraction": (c["n_null"] + c["n_masked"]) / max(flights, 1),
+        "paths": paths,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_LANE_OPS,
+                     "unit": "lane-ops/s", "frac": achieved / PEAK_LANE_OPS, "traffic": None,
+                     "kernel": "k_persistent<banded,slab>", "kernel_ms": k_ms,
+                     "ops_per_launch": ops},
+        "cpu_baseline": cpu,
+    }
+    run.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,235 @@
+/*
+ * avm.h -- C-ABI of the MI355X (gfx950) microscopic electron-avalanche
+ * transport library, libavm.so.
+ *
+ * What the library computes is the paper's AvalancheMicroscopic method
+ * (Sec. 2 and its Fig. 2; user interface in Sec. 3.2): electrons are carried
+ * collision by collision through a gas in an electric (and optional
+ * magnetic) field; every ionisation adds a secondary electron; the run ends
+ * when every electron has a non-zero status; the result is one endpoint per
+ * electron (start and end position, time and energy, status) and the
+ * per-avalanche gain (electrons after the avalanche / initial electrons,
+ * Sec. 2).  Free flights are null-collision flights (Skullerud, cited in
+ * Sec. 1) against a majorant rate taken from an energy-binned rate table.
+ *
+ * Conventions.
+ *  - Units: cm, ns, eV, V/cm, tesla, cm^2, cm^-3.
+ *  - Every call returns avm_status.  Nothing aborts or throws across the
+ *    ABI.  On error no handle is created and no output is written, except
+ *    AVM_E_CAPACITY (the run completed, but secondaries beyond the capacity
+ *    were dropped; see avm_counts.truncated).  avm_last_error() returns a
+ *    thread-local description of the last failing call on this thread.
+ *  - Handles are owned by the library and released with *_destroy.  A handle
+ *    is not thread-safe; distinct handles may be used from distinct threads.
+ *  - Input arrays are caller-owned host memory, copied during the call,
+ *    unless a parameter says "device pointer".
+ *  - All device work of a run is enqueued on the run's HIP stream.
+ */
+#ifndef AVM_H
+#define AVM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define AVM_ABI_VERSION 1
+
+typedef enum {
+  AVM_OK = 0,
+  AVM_E_ARG = 1,         /* invalid argument (message says which)                   */
+  AVM_E_NOMEM = 2,       /* host or device allocation failed                        */
+  AVM_E_HIP = 3,         /* a HIP runtime call failed (message carries its text)    */
+  AVM_E_CAPACITY = 4,    /* run finished but electrons beyond capacity were dropped */
+  AVM_E_UNSUPPORTED = 5, /* valid request this build does not implement             */
+  AVM_E_TIMEOUT = 6,     /* the run did not finish within the requested wall time   */
+  AVM_E_STATE = 7        /* call out of order (e.g. results before a run)           */
+} avm_status;
+
+/* Thread-local text of the last error on the calling thread ("" if none). */
+const char* avm_last_error(void);
+int32_t avm_abi_version(void);
+/* Number of HIP devices visible (0 when none); never fails. */
+int32_t avm_device_count(void);
+
+/* ------------------------------------------------------------------------ */
+/* Gas: energy-binned rate table                                             */
+/* ------------------------------------------------------------------------ */
+typedef enum { AVM_CH_ELASTIC = 0, AVM_CH_EXCITATION = 1, AVM_CH_IONISATION = 2, AVM_CH_ATTACHMENT = 3 } avm_channel_kind;
+typedef enum { AVM_ANG_ISOTROPIC = 0, AVM_ANG_SCREENED_RUTHERFORD = 1 } avm_angular;
+typedef enum { AVM_SPLIT_UNIFORM = 0, AVM_SPLIT_OPAL_BEATY = 1 } avm_split;
+typedef enum { AVM_VALUES_SIGMA = 0, AVM_VALUES_RATE = 1 } avm_values_kind;
+
+/* One collision channel, tabulated at the n_bins+1 nodes e_k = k E_max / n_bins. */
+typedef struct {
+  int32_t kind;        /* avm_channel_kind                                               */
+  int32_t angular;     /* elastic only: avm_angular                                      */
+  int32_t split;       /* ionisation only: avm_split                                     */
+  int32_t values_kind; /* AVM_VALUES_SIGMA: cm^2 (rate = N sigma v); AVM_VALUES_RATE: 1/ns */
+  double loss_eV;      /* excitation threshold / ionisation potential (0 otherwise)      */
+  double e_lo_eV;      /* the channel acts only for e in [e_lo, e_hi); interpolated rate */
+  double e_hi_eV;      /*   outside the window is a "masked" null collision (INFINITY ok) */
+  double mass_ratio;   /* elastic: electron mass / target mass                           */
+  double split_w_eV;   /* Opal-Beaty w: dsigma/de_s ~ 1/(1 + (e_s/w)^2) on [0, (e-I)/2] */
+  double screening_eV; /* screened Rutherford: eta(e) = screening / (8 e)               */
+  const double* values;/* host pointer, n_bins+1 node values (>= 0, finite); copied      */
+} avm_channel;
+
+typedef struct avm_gas avm_gas;
+
+/* Build the rate table on `device` (rate-table builder kernels): rates at the
+ * nodes, cumulative rates over channels (in the given order), per-bin maxima
+ * max(nu_k, nu_k+1) -- exact bounds of the linear interpolation -- the global
+ * majorant Gamma and, with band_bins > 0, band majorants Gamma_b = max of the
+ * per-bin maxima below the band's upper edge (bands of band_bins bins).
+ * Errors: AVM_E_ARG for n_channels < 1, n_bins < 1, e_max <= 0, negative or
+ * non-finite values, an excitation/ionisation window opening below its loss,
+ * or a table with no collisions at all.  Not timed work (done once per gas). */
+avm_status avm_gas_create(int32_t device, double e_max_eV, int32_t n_bins, double density_cm3,
+                          int32_t n_channels, const avm_channel* channels, int32_t band_bins,
+                          avm_gas** out);
+
+typedef struct {
+  double gamma;       /* global majorant, 1/ns */
+  double e_max_eV;
+  int32_t n_bins, n_channels, n_bands, band_bins;
+} avm_gas_info;
+
+avm_status avm_gas_get_info(const avm_gas* gas, avm_gas_info* out);
+/* Copy the device tables to host buffers (any may be NULL):
+ * cumulative [(n_bins+1) * n_channels] node-major; band_gamma and band_edge_eV
+ * [n_bands] (the last edge is +INFINITY). */
+avm_status avm_gas_get_tables(const avm_gas* gas, double* cumulative, double* band_gamma,
+                              double* band_edge_eV);
+void avm_gas_destroy(avm_gas* gas);
+
+/* ------------------------------------------------------------------------ */
+/* Fields                                                                    */
+/* ------------------------------------------------------------------------ */
+typedef struct avm_field avm_field;
+
+/* Parallel-plate slab z_lo <= z < z_hi (x, y unbounded), uniform field.
+ * E_vcm: host pointer to n_E field vectors [n_E][3]; n_E == 1 applies one
+ * field to every avalanche, otherwise avalanche a uses vector a.
+ * B_T: uniform magnetic field (may be NULL); it must be zero or along z.
+ * Electrons leaving through z_lo get status 1, through z_hi status 2. */
+avm_status avm_field_slab(int32_t device, double z_lo_cm, double z_hi_cm, uint32_t n_E,
+                          const double* E_vcm, const double* B_T, avm_field** out);
+
+/* Coaxial wire (radius a) inside a tube (radius b), field from a polar map:
+ * E_r and E_phi are host float arrays [n_r][n_phi] sampled at
+ * r_i = a (b/a)^(i/(n_r-1)), phi_j = 2 pi j / n_phi; the field is bilinear
+ * in (ln r, phi), clamped in r, periodic in phi.  B_T: uniform (may be NULL).
+ * Electrons reaching rho <= a get status 4, rho >= b status 5 (bisection of
+ * the flight on the inside/outside predicate). */
+avm_status avm_field_polar_map(int32_t device, double a_cm, double b_cm, int32_t n_r,
+                               int32_t n_phi, const float* E_r, const float* E_phi,
+                               const double* B_T, avm_field** out);
+void avm_field_destroy(avm_field* field);
+
+/* ------------------------------------------------------------------------ */
+/* Runs                                                                      */
+/* ------------------------------------------------------------------------ */
+/* A primary electron: position, time, kinetic energy, direction (normalised
+ * by the library; ignored at zero energy, where (0,0,1) is used), avalanche. */
+typedef struct {
+  double x, y, z, t, e, dx, dy, dz;
+  uint32_t avalanche, _pad;
+} avm_primary; /* 72 bytes */
+
+typedef enum { AVM_FP64 = 0, AVM_FP32_MIXED = 1 } avm_precision;
+typedef enum { AVM_MAJORANT_GLOBAL = 0, AVM_MAJORANT_BANDED = 1 } avm_majorant;
+typedef enum {
+  AVM_MODE_PLAIN = 0,  /* generation-synchronous loop of Fig. 2: one kernel per
+                          transport iteration, host reads the active count */
+  AVM_MODE_BATCHED = 1 /* one persistent kernel over every avalanche, fed by a
+                          device work queue; no host round trip */
+} avm_mode;
+
+typedef struct {
+  uint64_t seed;          /* Philox key                                                  */
+  int32_t precision;      /* avm_precision                                               */
+  int32_t majorant;       /* avm_majorant (banded needs B = 0 and band_bins > 0)          */
+  int32_t mode;           /* avm_mode                                                    */
+  int32_t flights_per_pass; /* batched: flights between queue visits (0: default)         */
+  double t_max_ns;        /* time limit (INFINITY: none) -> status 6                     */
+  uint64_t capacity;      /* electrons the run can hold (primaries included), >= n_prim  */
+  uint32_t k_max;         /* flights per electron before status 7; 0: 2^30-1             */
+  int32_t waves_per_cu;   /* batched: resident waves per CU (0: occupancy limit)          */
+  double timeout_s;       /* avm_run_sync wall-time limit (0: none) -> AVM_E_TIMEOUT      */
+  void* hip_stream;       /* hipStream_t for all of the run's work (NULL: null stream)    */
+} avm_run_opts;
+
+/* One electron's record.  status: 1 left z_lo, 2 left z_hi, 3 attached,
+ * 4 hit the wire, 5 reached the tube, 6 time limit, 7 flight limit,
+ * 8 numerical error.  eid: primaries 2^63 | index, secondaries 63-bit ids
+ * drawn from the parent's random stream; parent = 0 for primaries. */
+typedef struct {
+  double x0, y0, z0, t0, e0, x1, y1, z1, t1, e1;
+  uint64_t eid, parent;
+  uint32_t avalanche, status, n_real, n_ion, n_null, n_masked, n_band, n_overflow;
+} avm_endpoint; /* 128 bytes */
+
+/* Counters of a run (or of a range of avalanches).  gain of avalanche a =
+ * n_endpoints / number of its primaries. */
+typedef struct {
+  uint64_t n_endpoints; /* electrons, primaries included                          */
+  uint64_t n_ion;       /* ionisations = secondaries created                      */
+  uint64_t n_att;       /* attachments                                            */
+  uint64_t n_real;      /* real collisions (elastic+excitation+ionisation+attach) */
+  uint64_t n_null;      /* null collisions                                        */
+  uint64_t n_masked;    /* null because the chosen channel's window excludes e    */
+  uint64_t n_band;      /* flights cut at a band edge (banded majorant)            */
+  uint64_t n_overflow;  /* lookups above the table's last node                    */
+  uint64_t n_status[9]; /* electrons per status code                              */
+  uint64_t n_requested; /* electrons the run tried to create (> capacity: truncated) */
+  uint32_t truncated, _pad;
+} avm_counts;
+
+typedef struct avm_run avm_run;
+
+/* Prepare a run: validates, allocates the electron store (capacity
+ * electrons, ~200 bytes each) on the gas's device.  prim: n_prim records,
+ * a host pointer, or a device pointer when prim_on_device = 1 (it must stay
+ * valid until avm_run_sync returns).  n_aval: number of avalanches (every
+ * primary's avalanche id must be < n_aval, and < n_E for per-avalanche slab
+ * fields).  Gas and field must stay alive for the run's lifetime. */
+avm_status avm_run_create(const avm_gas* gas, const avm_field* field, const avm_primary* prim,
+                          int32_t prim_on_device, uint64_t n_prim, uint32_t n_aval,
+                          const avm_run_opts* opts, avm_run** out);
+/* Enqueue the run on its stream.  BATCHED: asynchronous.  PLAIN: returns
+ * when the generation loop has finished (it reads the active count back
+ * after every transport iteration, as the paper's stack processing does). */
+avm_status avm_run_execute(avm_run* run);
+/* Wait for the run, then fetch the totals.  AVM_E_CAPACITY if truncated. */
+avm_status avm_run_sync(avm_run* run);
+avm_status avm_run_counts(const avm_run* run, avm_counts* out);
+/* Per-avalanche counters for avalanches [first, first+n) (n_status and
+ * n_requested are zero in these records). */
+avm_status avm_run_avalanche_counts(const avm_run* run, uint32_t first, uint32_t n,
+                                    avm_counts* out);
+/* Number of endpoints stored (= min(n_requested, capacity)). */
+avm_status avm_run_num_endpoints(const avm_run* run, uint64_t* n);
+/* Copy endpoints [first, first+n) in storage order to host memory. */
+avm_status avm_run_endpoints(const avm_run* run, uint64_t first, uint64_t n, avm_endpoint* out);
+
+/* Device pointers to the endpoint arrays (structure of arrays, indexed by
+ * storage slot, valid until avm_run_destroy). */
+typedef struct {
+  const double *x0, *y0, *z0, *t0, *e0, *x1, *y1, *z1, *t1, *e1;
+  const uint64_t *eid, *parent;
+  const uint32_t *avalanche, *status, *n_real, *n_ion, *n_null, *n_masked, *n_band, *n_overflow;
+} avm_endpoint_arrays;
+avm_status avm_run_endpoint_arrays(const avm_run* run, avm_endpoint_arrays* out);
+
+/* Kernel time of the last execute (ms, HIP events on the run's stream
+ * around the transport kernels; plain mode: summed over iterations) and the
+ * number of transport iterations (plain) or 1 (batched). */
+avm_status avm_run_timing(const avm_run* run, double* transport_ms, uint32_t* iterations);
+void avm_run_destroy(avm_run* run);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -210,7 +210,9 @@ int orc_gas_create(double e_max_eV, int32_t n_bins, double density_cm3, int32_t 
     double m = 0.0;
     for (int32_t k = 0; k < kend; ++k)
       if (g->binmax[k] > m) m = g->binmax[k];
-    g->band_gamma[b] = m;
+    /* a band with no collisions at all below its edge keeps the global
+     * majorant (any bound >= the rate is valid; a zero one is not usable) */
+    g->band_gamma[b] = m > 0.0 ? m : g->gamma;
     g->band_edge[b] = ((double)kend * e_max_eV) / (double)n_bins;
   }
   *out = g;

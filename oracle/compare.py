@@ -1,0 +1,62 @@
+"""Per-trajectory comparison of an endpoint set against the oracle's.
+
+TEST INFRASTRUCTURE ONLY.  Both inputs are numpy structured arrays with the
+128-byte endpoint layout (fields x0..e1, eid, parent, aval, status and the
+per-electron counters); nothing here imports the HIP package.
+
+Electrons are joined on their id (primaries 2^63 | index, secondaries a
+63-bit id drawn from the parent's random stream), which is unique within a
+run with overwhelming probability.  A matched electron is a *flip* when its
+decision trace differs from the oracle's -- any counter or the status
+differs -- or when an end coordinate differs by more than the tolerance
+(|d| <= rtol * max(|ref|, floor), floors 1e-4 cm, 1e-3 ns, 1e-3 eV).  The
+descendants of a flipped electron carry different ids and show up as
+unmatched, not as flips.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+FLOORS = {"x0": 1e-4, "y0": 1e-4, "z0": 1e-4, "t0": 1e-3, "e0": 1e-3,
+          "x1": 1e-4, "y1": 1e-4, "z1": 1e-4, "t1": 1e-3, "e1": 1e-3}
+COUNTERS = ("aval", "status", "n_real", "n_ion", "n_null", "n_masked", "n_band", "n_overflow", "parent")
+
+
+def compare(got, ref, rtol=1e-9):
+    g_eid = got["eid"]
+    r_eid = ref["eid"]
+    if np.unique(g_eid).size != g_eid.size or np.unique(r_eid).size != r_eid.size:
+        raise AssertionError("duplicate electron ids inside one run")
+    common, gi, ri = np.intersect1d(g_eid, r_eid, assume_unique=True, return_indices=True)
+    G = got[gi]
+    R = ref[ri]
+    bad = np.zeros(common.size, dtype=bool)
+    max_rel = {}
+    for f, floor in FLOORS.items():
+        d = np.abs(G[f] - R[f])
+        scale = np.maximum(np.abs(R[f]), floor)
+        rel = d / scale
+        max_rel[f] = float(rel.max()) if rel.size else 0.0
+        bad |= ~(rel <= rtol)
+    for f in COUNTERS:
+        bad |= G[f] != R[f]
+    n_match = int(common.size)
+    return {
+        "n_got": int(got.size), "n_ref": int(ref.size), "matched": n_match,
+        "unmatched_got": int(got.size - n_match), "unmatched_ref": int(ref.size - n_match),
+        "flips": int(bad.sum()), "flip_fraction": float(bad.sum() / max(n_match, 1)),
+        "max_rel": max_rel,
+        "flipped_eids": common[bad][:20].tolist(),
+    }
+
+
+def assert_parity(got, ref, rtol=1e-9, max_flip_fraction=1e-3, max_unmatched_fraction=0.01):
+    rep = compare(got, ref, rtol)
+    assert rep["n_ref"] > 0
+    assert rep["flip_fraction"] < max_flip_fraction, rep
+    unm = max(rep["unmatched_got"], rep["unmatched_ref"]) / rep["n_ref"]
+    assert unm <= max_unmatched_fraction, rep
+    if rep["flips"] == 0:
+        # with no flip there is nothing to explain unmatched electrons by
+        assert rep["unmatched_got"] == 0 and rep["unmatched_ref"] == 0, rep
+    return rep

@@ -1,0 +1,784 @@
+// avm_api.cpp -- C-ABI of libavm (declared in include/avm.h): argument
+// validation, device memory, streams and the host side of the two
+// scheduling modes.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstddef>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <thread>
+#include <type_traits>
+#include <vector>
+
+#include "avm.h"
+#include "avm_internal.hpp"
+
+using namespace avm;
+
+namespace {
+
+thread_local std::string g_err;
+
+avm_status fail(avm_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+#define HIP_TRY(expr)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess) return fail(AVM_E_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+// Physical constants: speed of light, electron rest energy.
+constexpr double kCcmPerNs = 29.9792458;
+constexpr double kCmPerS = 299792458.0;
+constexpr double kMeC2eV = 510998.95;
+
+double k_a() { return (kCcmPerNs * kCcmPerNs) / kMeC2eV; }       // (cm/ns^2) / (V/cm)
+double k_b() { return 1e-9 * (kCmPerS * kCmPerS) / kMeC2eV; }    // rad / (ns T)
+
+// Makes `dev` current for the lifetime of the guard.
+struct DeviceGuard {
+  int prev = -1;
+  hipError_t err = hipSuccess;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    err = hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+template <class T>
+hipError_t dmalloc(T** p, size_t n) {
+  return hipMalloc(reinterpret_cast<void**>(p), sizeof(T) * (n ? n : 1));
+}
+
+}  // namespace
+
+struct avm_gas {
+  int device = 0;
+  double e_max = 0, density = 0, gamma = 0;
+  int32_t n_bins = 0, n_ch = 0, band_bins = 0, n_bands = 1;
+  double *cum = nullptr, *total = nullptr, *band_gamma = nullptr, *band_inv = nullptr,
+         *band_edge = nullptr;
+  ChanDev* ch = nullptr;
+  GasDev dev{};
+};
+
+struct avm_field {
+  int device = 0;
+  double B[3] = {0, 0, 0};
+  double* E = nullptr;
+  float *Er = nullptr, *Ephi = nullptr;
+  FieldDev dev{};
+};
+
+struct avm_run {
+  const avm_gas* gas = nullptr;
+  const avm_field* field = nullptr;
+  avm_run_opts opts{};
+  uint64_t n_prim = 0;
+  uint32_t n_aval = 0;
+  int prim_on_device = 0;
+  const PrimaryRec* prim_dev_user = nullptr;
+  PrimaryRec* prim_dev = nullptr;   // library copy (host primaries)
+  PrimaryRec* prim_host = nullptr;  // pinned staging
+  void* store_mem = nullptr;
+  Store S{};
+  uint32_t *list0 = nullptr, *list1 = nullptr;
+  Counters* ctr = nullptr;
+  AvalStats* stats = nullptr;
+  Totals* tot = nullptr;
+  Totals* tot_host = nullptr;      // pinned
+  Counters* ctr_host = nullptr;    // pinned
+  hipStream_t stream = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr, ev_done = nullptr;
+  uint32_t epoch = 0;
+  int executed = 0, synced = 0;
+  uint32_t iterations = 0;
+  double plain_ms = 0.0;
+  int grid = 0, block = 256;
+  int clock_khz = 100000;  // wall_clock64() rate
+};
+
+extern "C" {
+
+const char* avm_last_error(void) { return g_err.c_str(); }
+int32_t avm_abi_version(void) { return AVM_ABI_VERSION; }
+
+int32_t avm_device_count(void) {
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess) return 0;
+  return n;
+}
+
+// ---------------------------------------------------------------------------
+// gas
+// ---------------------------------------------------------------------------
+static void gas_free(avm_gas* g) {
+  if (!g) return;
+  (void)hipFree(g->cum);
+  (void)hipFree(g->total);
+  (void)hipFree(g->band_gamma);
+  (void)hipFree(g->band_inv);
+  (void)hipFree(g->band_edge);
+  (void)hipFree(g->ch);
+  delete g;
+}
+
+avm_status avm_gas_create(int32_t device, double e_max_eV, int32_t n_bins, double density_cm3,
+                          int32_t n_channels, const avm_channel* ch, int32_t band_bins,
+                          avm_gas** out) {
+  g_err.clear();
+  if (!out) return fail(AVM_E_ARG, "avm_gas_create: out is NULL");
+  *out = nullptr;
+  if (!ch || n_channels < 1) return fail(AVM_E_ARG, "avm_gas_create: need at least one channel");
+  if (n_bins < 1 || n_bins > (1 << 28)) return fail(AVM_E_ARG, "avm_gas_create: n_bins out of range");
+  if (!(e_max_eV > 0.0) || !std::isfinite(e_max_eV)) return fail(AVM_E_ARG, "avm_gas_create: e_max must be > 0");
+  if (!(density_cm3 >= 0.0) || !std::isfinite(density_cm3)) return fail(AVM_E_ARG, "avm_gas_create: bad density");
+  if (band_bins < 0) return fail(AVM_E_ARG, "avm_gas_create: band_bins < 0");
+  std::vector<ChanDev> cd(n_channels);
+  std::vector<int32_t> vk(n_channels);
+  const size_t nn = (size_t)n_bins + 1;
+  std::vector<double> sig(nn * n_channels);
+  for (int c = 0; c < n_channels; ++c) {
+    const avm_channel& x = ch[c];
+    if (!x.values) return fail(AVM_E_ARG, "channel %d: values is NULL", c);
+    if (x.kind < 0 || x.kind > 3) return fail(AVM_E_ARG, "channel %d: bad kind", c);
+    if (!(x.e_lo_eV <= x.e_hi_eV)) return fail(AVM_E_ARG, "channel %d: empty window", c);
+    if (!(x.loss_eV >= 0.0) || !std::isfinite(x.loss_eV)) return fail(AVM_E_ARG, "channel %d: bad loss", c);
+    if ((x.kind == AVM_CH_EXCITATION || x.kind == AVM_CH_IONISATION) && !(x.e_lo_eV >= x.loss_eV))
+      return fail(AVM_E_ARG, "channel %d: window opens below the energy loss", c);
+    if (x.kind == AVM_CH_ELASTIC && (!(x.mass_ratio >= 0.0) || !std::isfinite(x.mass_ratio)))
+      return fail(AVM_E_ARG, "channel %d: bad mass ratio", c);
+    if (x.kind == AVM_CH_ELASTIC && x.angular == AVM_ANG_SCREENED_RUTHERFORD && !(x.screening_eV > 0.0))
+      return fail(AVM_E_ARG, "channel %d: screened Rutherford needs screening_eV > 0", c);
+    if (x.kind == AVM_CH_IONISATION && x.split == AVM_SPLIT_OPAL_BEATY && !(x.split_w_eV > 0.0))
+      return fail(AVM_E_ARG, "channel %d: Opal-Beaty split needs w > 0", c);
+    if (x.values_kind != AVM_VALUES_SIGMA && x.values_kind != AVM_VALUES_RATE)
+      return fail(AVM_E_ARG, "channel %d: bad values_kind", c);
+    for (size_t k = 0; k < nn; ++k) {
+      const double v = x.values[k];
+      if (!(v >= 0.0) || !std::isfinite(v)) return fail(AVM_E_ARG, "channel %d node %zu: bad value", c, k);
+      sig[(size_t)c * nn + k] = v;
+    }
+    ChanDev& d = cd[c];
+    d.kind = x.kind;
+    d.angular = x.kind == AVM_CH_ELASTIC ? x.angular : 0;
+    d.split = x.kind == AVM_CH_IONISATION ? x.split : 0;
+    d.loss = x.loss_eV;
+    d.e_lo = x.e_lo_eV;
+    d.e_hi = x.e_hi_eV;
+    const double mu = x.kind == AVM_CH_ELASTIC ? x.mass_ratio : 0.0;
+    d.mu = mu;
+    d.el_loss = 2.0 * mu / ((1.0 + mu) * (1.0 + mu));
+    d.mu2p1 = 1.0 + mu * mu;
+    d.two_mu = 2.0 * mu;
+    d.split_w = x.split_w_eV;
+    d.atan_scale = x.split_w_eV > 0.0 ? 1.0 / (2.0 * x.split_w_eV) : 0.0;
+    d.inv_screen8 = x.screening_eV > 0.0 ? 8.0 / x.screening_eV : 0.0;
+    vk[c] = x.values_kind;
+  }
+  DeviceGuard dg(device);
+  if (dg.err != hipSuccess) return fail(AVM_E_HIP, "hipSetDevice(%d): %s", device, hipGetErrorString(dg.err));
+  avm_gas* g = new (std::nothrow) avm_gas();
+  if (!g) return fail(AVM_E_NOMEM, "host allocation");
+  g->device = device;
+  g->e_max = e_max_eV;
+  g->density = density_cm3;
+  g->n_bins = n_bins;
+  g->n_ch = n_channels;
+  g->band_bins = band_bins;
+  g->n_bands = band_bins > 0 ? (n_bins + band_bins - 1) / band_bins : 1;
+  double *d_sig = nullptr, *d_binmax = nullptr, *d_gamma = nullptr;
+  int32_t* d_vk = nullptr;
+  hipStream_t st = nullptr;
+  avm_status rc = AVM_OK;
+  auto cleanup = [&]() {
+    (void)hipFree(d_sig);
+    (void)hipFree(d_binmax);
+    (void)hipFree(d_gamma);
+    (void)hipFree(d_vk);
+    if (st) (void)hipStreamDestroy(st);
+  };
+  auto try_hip = [&](hipError_t e, const char* what) {
+    if (e != hipSuccess && rc == AVM_OK) rc = fail(e == hipErrorOutOfMemory ? AVM_E_NOMEM : AVM_E_HIP, "%s: %s", what, hipGetErrorString(e));
+    return e == hipSuccess;
+  };
+  bool ok = try_hip(hipStreamCreateWithFlags(&st, hipStreamNonBlocking), "hipStreamCreate") &&
+            try_hip(dmalloc(&d_sig, sig.size()), "hipMalloc") && try_hip(dmalloc(&d_vk, n_channels), "hipMalloc") &&
+            try_hip(dmalloc(&d_binmax, (size_t)n_bins), "hipMalloc") && try_hip(dmalloc(&d_gamma, 1), "hipMalloc") &&
+            try_hip(dmalloc(&g->cum, nn * n_channels), "hipMalloc") && try_hip(dmalloc(&g->total, nn), "hipMalloc") &&
+            try_hip(dmalloc(&g->band_gamma, (size_t)g->n_bands), "hipMalloc") &&
+            try_hip(dmalloc(&g->band_inv, (size_t)g->n_bands), "hipMalloc") &&
+            try_hip(dmalloc(&g->band_edge, (size_t)g->n_bands), "hipMalloc") &&
+            try_hip(dmalloc(&g->ch, (size_t)n_channels), "hipMalloc");
+  if (ok)
+    ok = try_hip(hipMemcpyAsync(d_sig, sig.data(), sizeof(double) * sig.size(), hipMemcpyHostToDevice, st), "H2D") &&
+         try_hip(hipMemcpyAsync(d_vk, vk.data(), sizeof(int32_t) * vk.size(), hipMemcpyHostToDevice, st), "H2D") &&
+         try_hip(hipMemcpyAsync(g->ch, cd.data(), sizeof(ChanDev) * cd.size(), hipMemcpyHostToDevice, st), "H2D") &&
+         try_hip(launch_build_rates(d_sig, d_vk, n_channels, n_bins, e_max_eV, density_cm3, k_a(), g->cum,
+                                    g->total, d_binmax, st), "rate-table kernels") &&
+         try_hip(launch_build_bands(d_binmax, n_bins, band_bins, g->n_bands, e_max_eV, g->band_gamma,
+                                    g->band_inv, g->band_edge, d_gamma, st), "band kernels");
+  double gamma = 0.0;
+  if (ok)
+    ok = try_hip(hipMemcpyAsync(&gamma, d_gamma, sizeof(double), hipMemcpyDeviceToHost, st), "D2H") &&
+         try_hip(hipStreamSynchronize(st), "hipStreamSynchronize");
+  cleanup();
+  if (!ok) {
+    gas_free(g);
+    return rc;
+  }
+  if (!(gamma > 0.0) || !std::isfinite(gamma)) {
+    gas_free(g);
+    return fail(AVM_E_ARG, "avm_gas_create: the table has no collisions (majorant %g)", gamma);
+  }
+  g->gamma = gamma;
+  GasDev& D = g->dev;
+  D.cum = g->cum;
+  D.total = g->total;
+  D.band_gamma = g->band_gamma;
+  D.band_inv = g->band_inv;
+  D.band_edge = g->band_edge;
+  D.ch = g->ch;
+  D.scale = (double)n_bins / e_max_eV;
+  D.gamma = gamma;
+  D.inv_gamma = 1.0 / gamma;
+  D.band_scale = band_bins > 0 ? (double)n_bins / (e_max_eV * (double)band_bins) : 0.0;
+  D.n_bins = n_bins;
+  D.n_ch = n_channels;
+  D.n_bands = g->n_bands;
+  D.band_bins = band_bins;
+  *out = g;
+  return AVM_OK;
+}
+
+avm_status avm_gas_get_info(const avm_gas* g, avm_gas_info* out) {
+  if (!g || !out) return fail(AVM_E_ARG, "avm_gas_get_info: NULL argument");
+  out->gamma = g->gamma;
+  out->e_max_eV = g->e_max;
+  out->n_bins = g->n_bins;
+  out->n_channels = g->n_ch;
+  out->n_bands = g->n_bands;
+  out->band_bins = g->band_bins;
+  return AVM_OK;
+}
+
+avm_status avm_gas_get_tables(const avm_gas* g, double* cumulative, double* band_gamma,
+                              double* band_edge_eV) {
+  if (!g) return fail(AVM_E_ARG, "avm_gas_get_tables: gas is NULL");
+  DeviceGuard dg(g->device);
+  if (cumulative)
+    HIP_TRY(hipMemcpy(cumulative, g->cum, sizeof(double) * ((size_t)g->n_bins + 1) * g->n_ch, hipMemcpyDeviceToHost));
+  if (band_gamma) HIP_TRY(hipMemcpy(band_gamma, g->band_gamma, sizeof(double) * g->n_bands, hipMemcpyDeviceToHost));
+  if (band_edge_eV) HIP_TRY(hipMemcpy(band_edge_eV, g->band_edge, sizeof(double) * g->n_bands, hipMemcpyDeviceToHost));
+  return AVM_OK;
+}
+
+void avm_gas_destroy(avm_gas* g) {
+  if (!g) return;
+  DeviceGuard dg(g->device);
+  gas_free(g);
+}
+
+// ---------------------------------------------------------------------------
+// fields
+// ---------------------------------------------------------------------------
+static void field_free(avm_field* f) {
+  if (!f) return;
+  (void)hipFree(f->E);
+  (void)hipFree(f->Er);
+  (void)hipFree(f->Ephi);
+  delete f;
+}
+
+static void set_bfield(avm_field* f, const double* B) {
+  FieldDev& D = f->dev;
+  if (B) {
+    f->B[0] = B[0];
+    f->B[1] = B[1];
+    f->B[2] = B[2];
+  }
+  const double bb = f->B[0] * f->B[0] + f->B[1] * f->B[1] + f->B[2] * f->B[2];
+  D.has_b = bb > 0.0;
+  if (D.has_b) {
+    const double bm = std::sqrt(bb);
+    for (int i = 0; i < 3; ++i) {
+      D.bh[i] = f->B[i] / bm;
+      D.Bv[i] = f->B[i];
+    }
+    D.omega = k_b() * bm;
+    D.inv_omega = 1.0 / D.omega;
+    D.wd_scale = (k_a() / k_b()) / bb;
+  }
+}
+
+static bool finite3(const double* B) {
+  return !B || (std::isfinite(B[0]) && std::isfinite(B[1]) && std::isfinite(B[2]));
+}
+
+avm_status avm_field_slab(int32_t device, double z_lo_cm, double z_hi_cm, uint32_t n_E,
+                          const double* E_vcm, const double* B_T, avm_field** out) {
+  g_err.clear();
+  if (!out) return fail(AVM_E_ARG, "avm_field_slab: out is NULL");
+  *out = nullptr;
+  if (!E_vcm || n_E < 1) return fail(AVM_E_ARG, "avm_field_slab: need n_E >= 1 field vectors");
+  if (!(z_lo_cm < z_hi_cm) || !std::isfinite(z_lo_cm) || !std::isfinite(z_hi_cm))
+    return fail(AVM_E_ARG, "avm_field_slab: need finite z_lo < z_hi");
+  if (!finite3(B_T)) return fail(AVM_E_ARG, "avm_field_slab: B not finite");
+  if (B_T && (B_T[0] != 0.0 || B_T[1] != 0.0))
+    return fail(AVM_E_UNSUPPORTED, "avm_field_slab: B must be zero or along z");
+  for (size_t i = 0; i < 3 * (size_t)n_E; ++i)
+    if (!std::isfinite(E_vcm[i])) return fail(AVM_E_ARG, "avm_field_slab: E not finite");
+  DeviceGuard dg(device);
+  if (dg.err != hipSuccess) return fail(AVM_E_HIP, "hipSetDevice(%d): %s", device, hipGetErrorString(dg.err));
+  avm_field* f = new (std::nothrow) avm_field();
+  if (!f) return fail(AVM_E_NOMEM, "host allocation");
+  f->device = device;
+  hipError_t e = dmalloc(&f->E, 3 * (size_t)n_E);
+  if (e == hipSuccess) e = hipMemcpy(f->E, E_vcm, sizeof(double) * 3 * n_E, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    field_free(f);
+    return fail(AVM_E_HIP, "avm_field_slab: %s", hipGetErrorString(e));
+  }
+  FieldDev& D = f->dev;
+  D.kind = FIELD_SLAB;
+  D.n_E = n_E;
+  D.z_lo = z_lo_cm;
+  D.z_hi = z_hi_cm;
+  D.E = f->E;
+  set_bfield(f, B_T);
+  *out = f;
+  return AVM_OK;
+}
+
+avm_status avm_field_polar_map(int32_t device, double a_cm, double b_cm, int32_t n_r, int32_t n_phi,
+                               const float* E_r, const float* E_phi, const double* B_T,
+                               avm_field** out) {
+  g_err.clear();
+  if (!out) return fail(AVM_E_ARG, "avm_field_polar_map: out is NULL");
+  *out = nullptr;
+  if (!E_r || !E_phi) return fail(AVM_E_ARG, "avm_field_polar_map: map is NULL");
+  if (!(a_cm > 0.0) || !(b_cm > a_cm) || !std::isfinite(b_cm)) return fail(AVM_E_ARG, "avm_field_polar_map: need 0 < a < b");
+  if (n_r < 2 || n_phi < 1 || (int64_t)n_r * n_phi > (1 << 28)) return fail(AVM_E_ARG, "avm_field_polar_map: bad map size");
+  if (!finite3(B_T)) return fail(AVM_E_ARG, "avm_field_polar_map: B not finite");
+  const size_t n = (size_t)n_r * n_phi;
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(E_r[i]) || !std::isfinite(E_phi[i])) return fail(AVM_E_ARG, "avm_field_polar_map: map not finite");
+  DeviceGuard dg(device);
+  if (dg.err != hipSuccess) return fail(AVM_E_HIP, "hipSetDevice(%d): %s", device, hipGetErrorString(dg.err));
+  avm_field* f = new (std::nothrow) avm_field();
+  if (!f) return fail(AVM_E_NOMEM, "host allocation");
+  f->device = device;
+  hipError_t e = dmalloc(&f->Er, n);
+  if (e == hipSuccess) e = dmalloc(&f->Ephi, n);
+  if (e == hipSuccess) e = hipMemcpy(f->Er, E_r, sizeof(float) * n, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(f->Ephi, E_phi, sizeof(float) * n, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    field_free(f);
+    return fail(AVM_E_HIP, "avm_field_polar_map: %s", hipGetErrorString(e));
+  }
+  FieldDev& D = f->dev;
+  D.kind = FIELD_POLAR;
+  D.a = a_cm;
+  D.b = b_cm;
+  D.a2 = a_cm * a_cm;
+  D.b2 = b_cm * b_cm;
+  D.inv_dlog = (double)(n_r - 1) / std::log(b_cm / a_cm);
+  D.ln_a = std::log(a_cm);
+  D.n_r = n_r;
+  D.n_phi = n_phi;
+  D.Er = f->Er;
+  D.Ephi = f->Ephi;
+  set_bfield(f, B_T);
+  *out = f;
+  return AVM_OK;
+}
+
+void avm_field_destroy(avm_field* f) {
+  if (!f) return;
+  DeviceGuard dg(f->device);
+  field_free(f);
+}
+
+// ---------------------------------------------------------------------------
+// runs
+// ---------------------------------------------------------------------------
+static void run_free(avm_run* r) {
+  if (!r) return;
+  (void)hipFree(r->store_mem);
+  (void)hipFree(r->list0);
+  (void)hipFree(r->list1);
+  (void)hipFree(r->ctr);
+  (void)hipFree(r->stats);
+  (void)hipFree(r->tot);
+  (void)hipFree(r->prim_dev);
+  if (r->prim_host) (void)hipHostFree(r->prim_host);
+  if (r->tot_host) (void)hipHostFree(r->tot_host);
+  if (r->ctr_host) (void)hipHostFree(r->ctr_host);
+  if (r->ev0) (void)hipEventDestroy(r->ev0);
+  if (r->ev1) (void)hipEventDestroy(r->ev1);
+  if (r->ev_done) (void)hipEventDestroy(r->ev_done);
+  delete r;
+}
+
+// Carves the structure-of-arrays electron store out of one allocation.
+static size_t layout_store(Store& S, char* base, uint64_t cap) {
+  size_t off = 0;
+  auto take = [&](auto** p, size_t elem) {
+    off = (off + 255) & ~size_t(255);
+    if (base) *p = reinterpret_cast<std::remove_pointer_t<decltype(p)>>(base + off);
+    off += elem * cap;
+  };
+  take(&S.x0, 8); take(&S.y0, 8); take(&S.z0, 8); take(&S.t0, 8);
+  take(&S.vx0, 8); take(&S.vy0, 8); take(&S.vz0, 8); take(&S.e0, 8);
+  take(&S.eid, 8); take(&S.parent, 8); take(&S.aval, 4); take(&S.ready, 4);
+  take(&S.x1, 8); take(&S.y1, 8); take(&S.z1, 8); take(&S.t1, 8); take(&S.e1, 8);
+  take(&S.vx1, 8); take(&S.vy1, 8); take(&S.vz1, 8);
+  take(&S.k1, 4); take(&S.band1, 4);
+  take(&S.status, 4); take(&S.n_real, 4); take(&S.n_ion, 4); take(&S.n_null, 4);
+  take(&S.n_masked, 4); take(&S.n_band, 4); take(&S.n_over, 4);
+  S.capacity = cap;
+  return off;
+}
+
+avm_status avm_run_create(const avm_gas* gas, const avm_field* field, const avm_primary* prim,
+                          int32_t prim_on_device, uint64_t n_prim, uint32_t n_aval,
+                          const avm_run_opts* opts, avm_run** out) {
+  g_err.clear();
+  if (!out) return fail(AVM_E_ARG, "avm_run_create: out is NULL");
+  *out = nullptr;
+  if (!gas || !field || !opts) return fail(AVM_E_ARG, "avm_run_create: NULL gas, field or opts");
+  if (gas->device != field->device) return fail(AVM_E_ARG, "avm_run_create: gas and field on different devices");
+  if (n_prim && !prim) return fail(AVM_E_ARG, "avm_run_create: primaries are NULL");
+  if (n_aval == 0 && n_prim) return fail(AVM_E_ARG, "avm_run_create: n_aval = 0");
+  if (field->dev.kind == FIELD_SLAB && field->dev.n_E > 1 && n_aval > field->dev.n_E)
+    return fail(AVM_E_ARG, "avm_run_create: %u avalanches but %u field vectors", n_aval, field->dev.n_E);
+  avm_run_opts o = *opts;
+  if (o.precision != AVM_FP64 && o.precision != AVM_FP32_MIXED) return fail(AVM_E_ARG, "avm_run_create: bad precision");
+  if (o.precision == AVM_FP32_MIXED) return fail(AVM_E_UNSUPPORTED, "avm_run_create: FP32-mixed precision is not built");
+  if (o.mode != AVM_MODE_PLAIN && o.mode != AVM_MODE_BATCHED) return fail(AVM_E_ARG, "avm_run_create: bad mode");
+  if (o.majorant != AVM_MAJORANT_GLOBAL && o.majorant != AVM_MAJORANT_BANDED) return fail(AVM_E_ARG, "avm_run_create: bad majorant");
+  if (o.majorant == AVM_MAJORANT_BANDED && gas->n_bands < 2)
+    return fail(AVM_E_ARG, "avm_run_create: banded majorant needs a gas built with band_bins > 0");
+  if (o.majorant == AVM_MAJORANT_BANDED && field->dev.has_b)
+    return fail(AVM_E_UNSUPPORTED, "avm_run_create: banded majorant needs B = 0");
+  if (o.k_max == 0) o.k_max = (1u << 30) - 1u;
+  if (o.k_max > (1u << 30) - 1u) return fail(AVM_E_ARG, "avm_run_create: k_max > 2^30-1");
+  if (std::isnan(o.t_max_ns)) return fail(AVM_E_ARG, "avm_run_create: t_max is NaN");
+  if (o.capacity == 0) o.capacity = n_prim * 64 > (1u << 20) ? n_prim * 64 : (1u << 20);
+  if (o.capacity < n_prim) return fail(AVM_E_ARG, "avm_run_create: capacity %llu < %llu primaries", (unsigned long long)o.capacity, (unsigned long long)n_prim);
+  if (o.capacity > 0xFFFFFFF0ull) return fail(AVM_E_ARG, "avm_run_create: capacity above 2^32-16");
+  if (o.flights_per_pass <= 0) o.flights_per_pass = 32;
+  if (o.waves_per_cu < 0) return fail(AVM_E_ARG, "avm_run_create: waves_per_cu < 0");
+  if (!prim_on_device)
+    for (uint64_t i = 0; i < n_prim; ++i) {
+      const avm_primary& p = prim[i];
+      if (p.avalanche >= n_aval) return fail(AVM_E_ARG, "primary %llu: avalanche %u >= n_aval", (unsigned long long)i, p.avalanche);
+      if (!std::isfinite(p.x) || !std::isfinite(p.y) || !std::isfinite(p.z) || !std::isfinite(p.t) ||
+          !(p.e >= 0.0) || !std::isfinite(p.e) || !std::isfinite(p.dx) || !std::isfinite(p.dy) || !std::isfinite(p.dz))
+        return fail(AVM_E_ARG, "primary %llu: non-finite or negative value", (unsigned long long)i);
+    }
+  DeviceGuard dg(gas->device);
+  if (dg.err != hipSuccess) return fail(AVM_E_HIP, "hipSetDevice: %s", hipGetErrorString(dg.err));
+  avm_run* r = new (std::nothrow) avm_run();
+  if (!r) return fail(AVM_E_NOMEM, "host allocation");
+  r->gas = gas;
+  r->field = field;
+  r->opts = o;
+  r->n_prim = n_prim;
+  r->n_aval = n_aval;
+  r->prim_on_device = prim_on_device;
+  r->stream = static_cast<hipStream_t>(o.hip_stream);
+  const uint64_t cap = o.capacity;
+  const size_t bytes = layout_store(r->S, nullptr, cap);
+  hipError_t e = hipMalloc(&r->store_mem, bytes);
+  if (e == hipSuccess) layout_store(r->S, static_cast<char*>(r->store_mem), cap);
+  if (e == hipSuccess) e = hipMemset(r->S.ready, 0, sizeof(uint32_t) * cap);
+  if (e == hipSuccess && o.mode == AVM_MODE_PLAIN) e = dmalloc(&r->list0, cap);
+  if (e == hipSuccess && o.mode == AVM_MODE_PLAIN) e = dmalloc(&r->list1, cap);
+  if (e == hipSuccess) e = dmalloc(&r->ctr, 1);
+  if (e == hipSuccess) e = dmalloc(&r->stats, n_aval ? n_aval : 1);
+  if (e == hipSuccess) e = dmalloc(&r->tot, 1);
+  if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&r->tot_host), sizeof(Totals), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&r->ctr_host), sizeof(Counters), hipHostMallocDefault);
+  if (e == hipSuccess && !prim_on_device && n_prim) {
+    e = dmalloc(&r->prim_dev, n_prim);
+    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&r->prim_host), sizeof(PrimaryRec) * n_prim, hipHostMallocDefault);
+    if (e == hipSuccess) std::memcpy(r->prim_host, prim, sizeof(PrimaryRec) * n_prim);
+  }
+  if (e == hipSuccess) {
+    int dev = 0, khz = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess && khz > 0)
+      r->clock_khz = khz;
+  }
+  if (e == hipSuccess) e = hipEventCreate(&r->ev0);
+  if (e == hipSuccess) e = hipEventCreate(&r->ev1);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&r->ev_done, hipEventDisableTiming);
+  if (e == hipSuccess && o.mode == AVM_MODE_BATCHED) {
+    int per_cu = 0, n_cu = 0, dev = 0;
+    e = persistent_occupancy(o.majorant == AVM_MAJORANT_BANDED, field->dev.kind, r->block, &per_cu);
+    if (e == hipSuccess) e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) {
+      if (per_cu < 1) per_cu = 1;
+      const int waves_per_block = r->block / 64;
+      if (o.waves_per_cu > 0) {
+        int want = (o.waves_per_cu + waves_per_block - 1) / waves_per_block;
+        per_cu = want < per_cu ? want : per_cu;
+      }
+      r->grid = per_cu * n_cu;
+    }
+  }
+  if (e != hipSuccess) {
+    const avm_status st = e == hipErrorOutOfMemory ? AVM_E_NOMEM : AVM_E_HIP;
+    run_free(r);
+    return fail(st, "avm_run_create: %s", hipGetErrorString(e));
+  }
+  if (prim_on_device) r->prim_dev_user = reinterpret_cast<const PrimaryRec*>(prim);
+  *out = r;
+  return AVM_OK;
+}
+
+static RunParams run_params(const avm_run* r) {
+  RunParams P{};
+  P.key0 = (uint32_t)r->opts.seed;
+  P.key1 = (uint32_t)(r->opts.seed >> 32);
+  P.k_max = r->opts.k_max;
+  P.banded = r->opts.majorant == AVM_MAJORANT_BANDED;
+  P.t_max = r->opts.t_max_ns;
+  P.k_a = k_a();
+  P.two_ka = 2.0 * P.k_a;
+  P.inv_2ka = 1.0 / P.two_ka;
+  // device time budget of one transport kernel: the caller's timeout, else
+  // a hard cap; a kernel past it stops and the run reports AVM_E_TIMEOUT
+  const double budget_s = r->opts.timeout_s > 0.0 ? r->opts.timeout_s : 600.0;
+  P.budget_ticks = (uint64_t)(budget_s * 1e3 * (double)r->clock_khz);
+  return P;
+}
+
+avm_status avm_run_execute(avm_run* r) {
+  g_err.clear();
+  if (!r) return fail(AVM_E_ARG, "avm_run_execute: run is NULL");
+  DeviceGuard dg(r->gas->device);
+  hipStream_t st = r->stream;
+  r->epoch += 1;
+  if (r->epoch == 0) r->epoch = 1;
+  r->executed = 1;
+  r->synced = 0;
+  const PrimaryRec* pd = r->prim_dev_user;
+  if (!r->prim_on_device && r->n_prim) {
+    HIP_TRY(hipMemcpyAsync(r->prim_dev, r->prim_host, sizeof(PrimaryRec) * r->n_prim, hipMemcpyHostToDevice, st));
+    pd = r->prim_dev;
+  }
+  const int plain = r->opts.mode == AVM_MODE_PLAIN;
+  HIP_TRY(launch_reset(r->ctr, r->n_prim, r->stats, r->n_aval, r->tot, st));
+  HIP_TRY(launch_load_primaries(pd, r->n_prim, r->S, r->epoch, k_a(), r->n_aval, r->list0, r->ctr, plain, st));
+  const RunParams P = run_params(r);
+  const int banded = r->opts.majorant == AVM_MAJORANT_BANDED;
+  const int fk = r->field->dev.kind;
+  if (plain) {
+    // the paper's loop: transport every active electron to its next
+    // ionisation or termination, then rebuild the active list, until none
+    // is left; the host reads the list size after each iteration
+    uint64_t n_active = r->n_prim;
+    uint32_t *A = r->list0, *B = r->list1;
+    r->iterations = 0;
+    r->plain_ms = 0.0;
+    while (n_active > 0) {
+      HIP_TRY(hipMemsetAsync(&r->ctr->next, 0, sizeof(unsigned long long), st));
+      HIP_TRY(hipEventRecord(r->ev0, st));
+      HIP_TRY(launch_generation(banded, fk, r->gas->dev, r->field->dev, P, r->S, A, (uint32_t)n_active, B, r->ctr, st));
+      HIP_TRY(hipEventRecord(r->ev1, st));
+      HIP_TRY(hipMemcpyAsync(r->ctr_host, r->ctr, sizeof(Counters), hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipStreamSynchronize(st));
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, r->ev0, r->ev1));
+      r->plain_ms += ms;
+      r->iterations += 1;
+      n_active = r->ctr_host->next;
+      if (r->ctr_host->timeout) break;
+      uint32_t* t = A;
+      A = B;
+      B = t;
+    }
+  } else {
+    HIP_TRY(hipEventRecord(r->ev0, st));
+    HIP_TRY(launch_persistent(banded, fk, r->gas->dev, r->field->dev, P, r->S, r->ctr, r->epoch,
+                              r->opts.flights_per_pass, r->grid, r->block, st));
+    HIP_TRY(hipEventRecord(r->ev1, st));
+    r->iterations = 1;
+  }
+  HIP_TRY(launch_stats(r->S, r->ctr, r->stats, r->tot, st));
+  HIP_TRY(hipMemcpyAsync(r->tot_host, r->tot, sizeof(Totals), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(r->ctr_host, r->ctr, sizeof(Counters), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipEventRecord(r->ev_done, st));
+  return AVM_OK;
+}
+
+avm_status avm_run_sync(avm_run* r) {
+  g_err.clear();
+  if (!r) return fail(AVM_E_ARG, "avm_run_sync: run is NULL");
+  if (!r->executed) return fail(AVM_E_STATE, "avm_run_sync: run not executed");
+  DeviceGuard dg(r->gas->device);
+  if (r->opts.timeout_s > 0.0) {
+    const auto t0 = std::chrono::steady_clock::now();
+    for (;;) {
+      const hipError_t q = hipEventQuery(r->ev_done);
+      if (q == hipSuccess) break;
+      if (q != hipErrorNotReady) return fail(AVM_E_HIP, "hipEventQuery: %s", hipGetErrorString(q));
+      const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      if (el > r->opts.timeout_s) return fail(AVM_E_TIMEOUT, "avm_run_sync: run still busy after %.1f s", el);
+      std::this_thread::sleep_for(std::chrono::microseconds(200));
+    }
+  } else {
+    HIP_TRY(hipEventSynchronize(r->ev_done));
+  }
+  r->synced = 1;
+  if (r->ctr_host->timeout) return fail(AVM_E_TIMEOUT, "avm_run_sync: a transport kernel exceeded its time budget");
+  if (r->ctr_host->err) return fail(AVM_E_ARG, "avm_run_sync: %llu primaries had an avalanche id >= n_aval", r->ctr_host->err);
+  if (r->ctr_host->tail > r->S.capacity)
+    return fail(AVM_E_CAPACITY, "avm_run_sync: %llu electrons requested, capacity %llu", r->ctr_host->tail, (unsigned long long)r->S.capacity);
+  return AVM_OK;
+}
+
+avm_status avm_run_counts(const avm_run* r, avm_counts* out) {
+  if (!r || !out) return fail(AVM_E_ARG, "avm_run_counts: NULL argument");
+  if (!r->synced) return fail(AVM_E_STATE, "avm_run_counts: call avm_run_sync first");
+  std::memset(out, 0, sizeof *out);
+  const Totals& T = *r->tot_host;
+  out->n_endpoints = T.c[0];
+  out->n_ion = T.c[1];
+  out->n_att = T.c[2];
+  out->n_real = T.c[3];
+  out->n_null = T.c[4];
+  out->n_masked = T.c[5];
+  out->n_band = T.c[6];
+  out->n_overflow = T.c[7];
+  for (int i = 0; i < 9; ++i) out->n_status[i] = T.status[i];
+  out->n_requested = r->ctr_host->tail;
+  out->truncated = r->ctr_host->tail > r->S.capacity;
+  return AVM_OK;
+}
+
+avm_status avm_run_avalanche_counts(const avm_run* r, uint32_t first, uint32_t n, avm_counts* out) {
+  if (!r || (!out && n)) return fail(AVM_E_ARG, "avm_run_avalanche_counts: NULL argument");
+  if (!r->synced) return fail(AVM_E_STATE, "avm_run_avalanche_counts: call avm_run_sync first");
+  if ((uint64_t)first + n > r->n_aval) return fail(AVM_E_ARG, "avm_run_avalanche_counts: range beyond n_aval");
+  if (n == 0) return AVM_OK;
+  DeviceGuard dg(r->gas->device);
+  std::vector<AvalStats> h(n);
+  HIP_TRY(hipMemcpy(h.data(), r->stats + first, sizeof(AvalStats) * n, hipMemcpyDeviceToHost));
+  for (uint32_t i = 0; i < n; ++i) {
+    avm_counts& c = out[i];
+    std::memset(&c, 0, sizeof c);
+    c.n_endpoints = h[i].n_endpoints;
+    c.n_ion = h[i].n_ion;
+    c.n_att = h[i].n_att;
+    c.n_real = h[i].n_real;
+    c.n_null = h[i].n_null;
+    c.n_masked = h[i].n_masked;
+    c.n_band = h[i].n_band;
+    c.n_overflow = h[i].n_over;
+  }
+  return AVM_OK;
+}
+
+avm_status avm_run_num_endpoints(const avm_run* r, uint64_t* n) {
+  if (!r || !n) return fail(AVM_E_ARG, "avm_run_num_endpoints: NULL argument");
+  if (!r->synced) return fail(AVM_E_STATE, "avm_run_num_endpoints: call avm_run_sync first");
+  *n = r->ctr_host->tail < r->S.capacity ? r->ctr_host->tail : r->S.capacity;
+  return AVM_OK;
+}
+
+avm_status avm_run_endpoints(const avm_run* r, uint64_t first, uint64_t n, avm_endpoint* out) {
+  if (!r || (!out && n)) return fail(AVM_E_ARG, "avm_run_endpoints: NULL argument");
+  uint64_t total = 0;
+  avm_status s = avm_run_num_endpoints(r, &total);
+  if (s != AVM_OK) return s;
+  if (first > total || n > total - first) return fail(AVM_E_ARG, "avm_run_endpoints: range beyond the stored endpoints");
+  if (n == 0) return AVM_OK;
+  DeviceGuard dg(r->gas->device);
+  const Store& S = r->S;
+  std::vector<double> d(n);
+  std::vector<uint64_t> q(n);
+  std::vector<uint32_t> u(n);
+  auto getd = [&](const double* src, size_t off) -> avm_status {
+    HIP_TRY(hipMemcpy(d.data(), src + first, sizeof(double) * n, hipMemcpyDeviceToHost));
+    for (uint64_t i = 0; i < n; ++i) std::memcpy(reinterpret_cast<char*>(&out[i]) + off, &d[i], 8);
+    return AVM_OK;
+  };
+  auto getq = [&](const uint64_t* src, size_t off) -> avm_status {
+    HIP_TRY(hipMemcpy(q.data(), src + first, sizeof(uint64_t) * n, hipMemcpyDeviceToHost));
+    for (uint64_t i = 0; i < n; ++i) std::memcpy(reinterpret_cast<char*>(&out[i]) + off, &q[i], 8);
+    return AVM_OK;
+  };
+  auto getu = [&](const uint32_t* src, size_t off) -> avm_status {
+    HIP_TRY(hipMemcpy(u.data(), src + first, sizeof(uint32_t) * n, hipMemcpyDeviceToHost));
+    for (uint64_t i = 0; i < n; ++i) std::memcpy(reinterpret_cast<char*>(&out[i]) + off, &u[i], 4);
+    return AVM_OK;
+  };
+#define AVM_GET(fn, arr, field) \
+  if ((s = fn(S.arr, offsetof(avm_endpoint, field))) != AVM_OK) return s
+  AVM_GET(getd, x0, x0); AVM_GET(getd, y0, y0); AVM_GET(getd, z0, z0); AVM_GET(getd, t0, t0);
+  AVM_GET(getd, e0, e0); AVM_GET(getd, x1, x1); AVM_GET(getd, y1, y1); AVM_GET(getd, z1, z1);
+  AVM_GET(getd, t1, t1); AVM_GET(getd, e1, e1);
+  AVM_GET(getq, eid, eid); AVM_GET(getq, parent, parent);
+  AVM_GET(getu, aval, avalanche); AVM_GET(getu, status, status); AVM_GET(getu, n_real, n_real);
+  AVM_GET(getu, n_ion, n_ion); AVM_GET(getu, n_null, n_null); AVM_GET(getu, n_masked, n_masked);
+  AVM_GET(getu, n_band, n_band); AVM_GET(getu, n_over, n_overflow);
+#undef AVM_GET
+  return AVM_OK;
+}
+
+avm_status avm_run_endpoint_arrays(const avm_run* r, avm_endpoint_arrays* out) {
+  if (!r || !out) return fail(AVM_E_ARG, "avm_run_endpoint_arrays: NULL argument");
+  const Store& S = r->S;
+  out->x0 = S.x0; out->y0 = S.y0; out->z0 = S.z0; out->t0 = S.t0; out->e0 = S.e0;
+  out->x1 = S.x1; out->y1 = S.y1; out->z1 = S.z1; out->t1 = S.t1; out->e1 = S.e1;
+  out->eid = S.eid; out->parent = S.parent; out->avalanche = S.aval; out->status = S.status;
+  out->n_real = S.n_real; out->n_ion = S.n_ion; out->n_null = S.n_null; out->n_masked = S.n_masked;
+  out->n_band = S.n_band; out->n_overflow = S.n_over;
+  return AVM_OK;
+}
+
+avm_status avm_run_timing(const avm_run* r, double* transport_ms, uint32_t* iterations) {
+  if (!r) return fail(AVM_E_ARG, "avm_run_timing: run is NULL");
+  if (!r->synced) return fail(AVM_E_STATE, "avm_run_timing: call avm_run_sync first");
+  if (transport_ms) {
+    if (r->opts.mode == AVM_MODE_PLAIN) {
+      *transport_ms = r->plain_ms;
+    } else {
+      float ms = 0.f;
+      DeviceGuard dg(r->gas->device);
+      HIP_TRY(hipEventElapsedTime(&ms, r->ev0, r->ev1));
+      *transport_ms = ms;
+    }
+  }
+  if (iterations) *iterations = r->iterations;
+  return AVM_OK;
+}
+
+void avm_run_destroy(avm_run* r) {
+  if (!r) return;
+  DeviceGuard dg(r->gas->device);
+  if (r->executed && !r->synced) (void)hipEventSynchronize(r->ev_done);
+  run_free(r);
+}
+
+}  // extern "C"

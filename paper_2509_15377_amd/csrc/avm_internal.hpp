@@ -1,0 +1,76 @@
+// avm_internal.hpp -- host-side structures shared by the C-ABI layer and the
+// kernel launchers of libavm (not installed; the public interface is avm.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "avm_device.hpp"
+
+namespace avm {
+
+// Device store of a run, structure of arrays indexed by slot.  Slot s holds
+// the s-th electron created: its start record (written when it is created)
+// and its end record (written when it terminates).  The plain mode also
+// keeps the state of live electrons between transport iterations in the end
+// record (x1..t1 = current position, v1 = current velocity).
+struct Store {
+  double *x0, *y0, *z0, *t0, *vx0, *vy0, *vz0, *e0;
+  uint64_t *eid, *parent;
+  uint32_t* aval;
+  uint32_t* ready;  // batched: slot published when ready[s] == epoch
+  double *x1, *y1, *z1, *t1, *e1, *vx1, *vy1, *vz1;
+  uint32_t *k1, *band1;
+  uint32_t *status, *n_real, *n_ion, *n_null, *n_masked, *n_band, *n_over;
+  uint64_t capacity;
+};
+
+// Device counters of a run.
+struct Counters {
+  unsigned long long tail;     // slots requested (electrons created, incl. dropped)
+  unsigned long long head;     // batched: slots claimed by lanes
+  unsigned long long live;     // batched: electrons created and not yet terminated
+  unsigned long long next;     // plain: size of the next active list
+  unsigned long long err;      // bad primary avalanche id
+  unsigned long long timeout;  // a transport kernel ran out of its time budget
+  unsigned long long _pad[2];
+};
+
+// Per-avalanche statistics (and totals, with the status histogram).
+struct AvalStats {
+  unsigned long long n_endpoints, n_ion, n_att, n_real, n_null, n_masked, n_band, n_over;
+};
+struct Totals {
+  unsigned long long c[8];       // as AvalStats
+  unsigned long long status[9];
+  unsigned long long _pad[7];
+};
+
+struct PrimaryRec {
+  double x, y, z, t, e, dx, dy, dz;
+  uint32_t aval, _pad;
+};
+
+// ---- launchers (avm_kernels.hip) ----
+hipError_t launch_build_rates(const double* sigma, const int32_t* values_kind, int n_ch, int n_bins,
+                              double e_max, double density, double k_a, double* cum, double* total,
+                              double* binmax, hipStream_t st);
+hipError_t launch_build_bands(const double* binmax, int n_bins, int band_bins, int n_bands,
+                              double e_max, double* band_gamma, double* band_inv, double* band_edge,
+                              double* gamma_out, hipStream_t st);
+hipError_t launch_load_primaries(const PrimaryRec* prim, uint64_t n, const Store& S, uint32_t epoch,
+                                 double k_a, uint32_t n_aval, uint32_t* active, Counters* ctr,
+                                 int plain, hipStream_t st);
+hipError_t launch_reset(Counters* ctr, uint64_t n_prim, AvalStats* stats, uint32_t n_aval,
+                        Totals* tot, hipStream_t st);
+hipError_t launch_generation(int banded, int field_kind, const GasDev& G, const FieldDev& F,
+                             const RunParams& P, const Store& S, const uint32_t* active,
+                             uint32_t n_active, uint32_t* next, Counters* ctr, hipStream_t st);
+hipError_t launch_persistent(int banded, int field_kind, const GasDev& G, const FieldDev& F,
+                             const RunParams& P, const Store& S, Counters* ctr, uint32_t epoch,
+                             int flights_per_pass, int grid, int block, hipStream_t st);
+hipError_t persistent_occupancy(int banded, int field_kind, int block, int* blocks_per_cu);
+hipError_t launch_stats(const Store& S, const Counters* ctr, AvalStats* stats, Totals* tot,
+                        hipStream_t st);
+
+}  // namespace avm
