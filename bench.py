@@ -37,6 +37,9 @@ def parse():
     ap.add_argument("--workload", default="argon")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-mode reference leg")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the FP32-mixed leg")
+    ap.add_argument("--eager", action="store_true",
+                    help="launch the batched run eagerly instead of replaying its HIP graph")
     return ap.parse_args()
 
 
@@ -61,24 +64,29 @@ def main():
     field = avm.Field(wl.field, 0)
     capacity = 16_000_000
 
-    def make(mode, majorant, precision=avm.FP64):
+    use_graph = not args.eager
+
+    def make(mode, majorant, precision=avm.FP64, graph=False):
         return avm.Run(gas, field, prim_dev, wl.n_aval, seed=wl.seed, precision=precision,
                        majorant=majorant, mode=mode, capacity=capacity, timeout_s=300.0,
-                       stream=stream)
+                       stream=stream, graph=graph)
 
-    run = make(avm.BATCHED, avm.BANDED)
-    for _ in range(args.warmup):
-        run.execute()
-        run.sync()
-    torch.cuda.synchronize()
-    kernel_ms = []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        run.execute()
-        run.sync()
-        kernel_ms.append(run.timing()[0])
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+    def timed(run):
+        for _ in range(args.warmup):
+            run.execute()
+            run.sync()
+        torch.cuda.synchronize()
+        kms = []
+        t = time.perf_counter()
+        for _ in range(args.steps):
+            run.execute()
+            run.sync()
+            kms.append(run.timing()[0])
+        torch.cuda.synchronize()
+        return time.perf_counter() - t, kms
+
+    run = make(avm.BATCHED, avm.BANDED, graph=use_graph)
+    wall, kernel_ms = timed(run)
     c = run.counts()
     flights = c["n_real"] + c["n_null"] + c["n_masked"] + c["n_band"]
     ms_step = wall * 1e3 / args.steps
@@ -90,7 +98,22 @@ def main():
     paths = {"batched_fp64_banded": {"real_collisions_per_s": value,
                                      "secondaries_per_s": c["n_ion"] / (ms_step * 1e-3),
                                      "flights_per_s": flights / (ms_step * 1e-3),
-                                     "ms_per_step": ms_step, "kernel_ms": k_ms}}
+                                     "ms_per_step": ms_step, "kernel_ms": k_ms,
+                                     "graph": use_graph}}
+    if not args.no_mixed:
+        # FP32 arithmetic in the flight loop, FP64 positions/times and
+        # re-decided close calls (statistically equivalent, not per-trajectory)
+        mr = make(avm.BATCHED, avm.BANDED, precision=avm.FP32_MIXED, graph=use_graph)
+        mw, mk = timed(mr)
+        mc = mr.counts()
+        mms = mw * 1e3 / args.steps
+        paths["batched_fp32mixed_banded"] = {
+            "real_collisions_per_s": mc["n_real"] / (mms * 1e-3),
+            "secondaries_per_s": mc["n_ion"] / (mms * 1e-3),
+            "flights_per_s": (mc["n_real"] + mc["n_null"] + mc["n_masked"] + mc["n_band"]) / (mms * 1e-3),
+            "ms_per_step": mms, "kernel_ms": sum(mk) / len(mk),
+            "mean_gain": mc["n_endpoints"] / wl.n_aval, "graph": use_graph}
+        mr.close()
     if not args.no_plain:
         # the paper's scheduling (one kernel per transport iteration, host
         # reads the active count back) with the global majorant, one pass

@@ -138,6 +138,12 @@ typedef struct {
   uint32_t avalanche, _pad;
 } avm_primary; /* 72 bytes */
 
+/* FP64: every step in double precision.  FP32_MIXED: velocities, flight
+ * times, energies, table interpolation and scattering in single precision,
+ * position and time accumulated in double, boundary crossings solved in
+ * double, and a collision decision whose single-precision margin is below
+ * 2^-18 taken again in double; it draws the same random blocks as FP64
+ * (24-bit uniforms from the same words), so the two are paired runs. */
 typedef enum { AVM_FP64 = 0, AVM_FP32_MIXED = 1 } avm_precision;
 typedef enum { AVM_MAJORANT_GLOBAL = 0, AVM_MAJORANT_BANDED = 1 } avm_majorant;
 typedef enum {
@@ -159,6 +165,10 @@ typedef struct {
   int32_t waves_per_cu;   /* batched: resident waves per CU (0: occupancy limit)          */
   double timeout_s;       /* avm_run_sync wall-time limit (0: none) -> AVM_E_TIMEOUT      */
   void* hip_stream;       /* hipStream_t for all of the run's work (NULL: null stream)    */
+  int32_t graph;          /* batched: 1 = capture the run's device work (reset, primary  */
+                          /*   load, transport, statistics, result copies) into a HIP    */
+                          /*   graph on the first execute and replay it afterwards       */
+  int32_t _pad1;
 } avm_run_opts;
 
 /* One electron's record.  status: 1 left z_lo, 2 left z_hi, 3 attached,
@@ -224,8 +234,9 @@ typedef struct {
 avm_status avm_run_endpoint_arrays(const avm_run* run, avm_endpoint_arrays* out);
 
 /* Kernel time of the last execute (ms, HIP events on the run's stream
- * around the transport kernels; plain mode: summed over iterations) and the
- * number of transport iterations (plain) or 1 (batched). */
+ * around the transport kernels; plain mode: summed over iterations; graph
+ * mode: the whole replayed graph) and the number of transport iterations
+ * (plain) or 1 (batched). */
 avm_status avm_run_timing(const avm_run* run, double* transport_ms, uint32_t* iterations);
 void avm_run_destroy(avm_run* run);
 

@@ -57,7 +57,8 @@ class _Opts(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("precision", C.c_int32), ("majorant", C.c_int32),
                 ("mode", C.c_int32), ("flights_per_pass", C.c_int32), ("t_max_ns", C.c_double),
                 ("capacity", C.c_uint64), ("k_max", C.c_uint32), ("waves_per_cu", C.c_int32),
-                ("timeout_s", C.c_double), ("hip_stream", C.c_void_p)]
+                ("timeout_s", C.c_double), ("hip_stream", C.c_void_p), ("graph", C.c_int32),
+                ("_pad1", C.c_int32)]
 
 
 class _Counts(C.Structure):
@@ -184,7 +185,11 @@ class Gas:
             lib().avm_gas_destroy(self.h)
             self.h = None
 
-    __del__ = close
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # interpreter shutdown: the library may be gone
+            pass
 
 
 class Field:
@@ -209,7 +214,11 @@ class Field:
             lib().avm_field_destroy(self.h)
             self.h = None
 
-    __del__ = close
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # interpreter shutdown: the library may be gone
+            pass
 
 
 def _counts_dict(c: _Counts):
@@ -227,7 +236,8 @@ class Run:
 
     def __init__(self, gas: Gas, field: Field, primaries, n_aval: int, *, seed: int,
                  precision=FP64, majorant=GLOBAL, mode=BATCHED, capacity=0, t_max=math.inf,
-                 k_max=0, flights_per_pass=0, waves_per_cu=0, timeout_s=0.0, stream=None):
+                 k_max=0, flights_per_pass=0, waves_per_cu=0, timeout_s=0.0, stream=None,
+                 graph=False):
         self._keep = [gas, field, primaries]
         on_dev = 0
         if hasattr(primaries, "data_ptr"):  # torch tensor
@@ -249,7 +259,7 @@ class Run:
         if stream is not None:
             st = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
         o = _Opts(int(seed), precision, majorant, mode, int(flights_per_pass), float(t_max),
-                  int(capacity), int(k_max), int(waves_per_cu), float(timeout_s), st)
+                  int(capacity), int(k_max), int(waves_per_cu), float(timeout_s), st, int(bool(graph)), 0)
         h = _VP()
         _check(lib().avm_run_create(gas.h, field.h, ptr, on_dev, n_prim, int(n_aval), C.byref(o),
                                     C.byref(h)), "avm_run_create")
@@ -308,7 +318,11 @@ class Run:
             lib().avm_run_destroy(self.h)
             self.h = None
 
-    __del__ = close
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # interpreter shutdown: the library may be gone
+            pass
 
 
 def run(workload=None, *, gas=None, field=None, primaries=None, n_aval=None, seed=None,

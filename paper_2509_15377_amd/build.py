@@ -15,9 +15,13 @@ SOURCES = ["avm_kernels.hip", "avm_api.cpp"]
 
 # -ffp-contract=off: no implicit a*b+c fusion, so a device function gives the
 # same bits in every kernel that inlines it.  Packed FP32 instructions are
-# disabled for all device code.
+# disabled for all device code.  Machine-level loop-invariant code motion is
+# off: it hoists the FP64 polynomial constants of the transcendental
+# functions out of the transport loop into ~100 VGPRs, which halves the
+# transport kernels' occupancy.
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
+    "-mllvm", "-disable-machine-licm",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function",
 ]

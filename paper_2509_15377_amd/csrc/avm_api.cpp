@@ -72,9 +72,13 @@ struct avm_gas {
   int device = 0;
   double e_max = 0, density = 0, gamma = 0;
   int32_t n_bins = 0, n_ch = 0, band_bins = 0, n_bands = 1;
-  double *cum = nullptr, *total = nullptr, *band_gamma = nullptr, *band_inv = nullptr,
-         *band_edge = nullptr;
+  double *cum = nullptr, *cum0 = nullptr, *total = nullptr, *band_gamma = nullptr,
+         *band_inv = nullptr, *band_edge = nullptr;
   ChanDev* ch = nullptr;
+  // FP32 copies for the FP32-mixed path
+  float *cum_f = nullptr, *cum0_f = nullptr, *total_f = nullptr, *band_gamma_f = nullptr,
+        *band_inv_f = nullptr, *band_edge_f = nullptr;
+  ChanP<float>* ch_f = nullptr;
   GasDev dev{};
 };
 
@@ -106,11 +110,12 @@ struct avm_run {
   Counters* ctr_host = nullptr;    // pinned
   hipStream_t stream = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr, ev_done = nullptr;
-  uint32_t epoch = 0;
   int executed = 0, synced = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
   uint32_t iterations = 0;
   double plain_ms = 0.0;
-  int grid = 0, block = 256;
+  int grid = 0, block = 512;
   int clock_khz = 100000;  // wall_clock64() rate
 };
 
@@ -131,11 +136,19 @@ int32_t avm_device_count(void) {
 static void gas_free(avm_gas* g) {
   if (!g) return;
   (void)hipFree(g->cum);
+  (void)hipFree(g->cum0);
   (void)hipFree(g->total);
   (void)hipFree(g->band_gamma);
   (void)hipFree(g->band_inv);
   (void)hipFree(g->band_edge);
   (void)hipFree(g->ch);
+  (void)hipFree(g->cum_f);
+  (void)hipFree(g->cum0_f);
+  (void)hipFree(g->total_f);
+  (void)hipFree(g->band_gamma_f);
+  (void)hipFree(g->band_inv_f);
+  (void)hipFree(g->band_edge_f);
+  (void)hipFree(g->ch_f);
   delete g;
 }
 
@@ -151,6 +164,7 @@ avm_status avm_gas_create(int32_t device, double e_max_eV, int32_t n_bins, doubl
   if (!(density_cm3 >= 0.0) || !std::isfinite(density_cm3)) return fail(AVM_E_ARG, "avm_gas_create: bad density");
   if (band_bins < 0) return fail(AVM_E_ARG, "avm_gas_create: band_bins < 0");
   std::vector<ChanDev> cd(n_channels);
+  std::vector<ChanP<float>> cf(n_channels);
   std::vector<int32_t> vk(n_channels);
   const size_t nn = (size_t)n_bins + 1;
   std::vector<double> sig(nn * n_channels);
@@ -190,6 +204,20 @@ avm_status avm_gas_create(int32_t device, double e_max_eV, int32_t n_bins, doubl
     d.split_w = x.split_w_eV;
     d.atan_scale = x.split_w_eV > 0.0 ? 1.0 / (2.0 * x.split_w_eV) : 0.0;
     d.inv_screen8 = x.screening_eV > 0.0 ? 8.0 / x.screening_eV : 0.0;
+    ChanP<float>& q = cf[c];
+    q.kind = d.kind;
+    q.angular = d.angular;
+    q.split = d.split;
+    q.e_lo = d.e_lo;
+    q.e_hi = d.e_hi;
+    q.loss = (float)d.loss;
+    q.mu = (float)d.mu;
+    q.el_loss = (float)d.el_loss;
+    q.mu2p1 = (float)d.mu2p1;
+    q.two_mu = (float)d.two_mu;
+    q.split_w = (float)d.split_w;
+    q.atan_scale = (float)d.atan_scale;
+    q.inv_screen8 = (float)d.inv_screen8;
     vk[c] = x.values_kind;
   }
   DeviceGuard dg(device);
@@ -222,18 +250,32 @@ avm_status avm_gas_create(int32_t device, double e_max_eV, int32_t n_bins, doubl
             try_hip(dmalloc(&d_sig, sig.size()), "hipMalloc") && try_hip(dmalloc(&d_vk, n_channels), "hipMalloc") &&
             try_hip(dmalloc(&d_binmax, (size_t)n_bins), "hipMalloc") && try_hip(dmalloc(&d_gamma, 1), "hipMalloc") &&
             try_hip(dmalloc(&g->cum, nn * n_channels), "hipMalloc") && try_hip(dmalloc(&g->total, nn), "hipMalloc") &&
+            try_hip(dmalloc(&g->cum0, nn), "hipMalloc") &&
             try_hip(dmalloc(&g->band_gamma, (size_t)g->n_bands), "hipMalloc") &&
             try_hip(dmalloc(&g->band_inv, (size_t)g->n_bands), "hipMalloc") &&
             try_hip(dmalloc(&g->band_edge, (size_t)g->n_bands), "hipMalloc") &&
-            try_hip(dmalloc(&g->ch, (size_t)n_channels), "hipMalloc");
+            try_hip(dmalloc(&g->ch, (size_t)n_channels), "hipMalloc") &&
+            try_hip(dmalloc(&g->ch_f, (size_t)n_channels), "hipMalloc") &&
+            try_hip(dmalloc(&g->cum_f, nn * n_channels), "hipMalloc") &&
+            try_hip(dmalloc(&g->cum0_f, nn), "hipMalloc") && try_hip(dmalloc(&g->total_f, nn), "hipMalloc") &&
+            try_hip(dmalloc(&g->band_gamma_f, (size_t)g->n_bands), "hipMalloc") &&
+            try_hip(dmalloc(&g->band_inv_f, (size_t)g->n_bands), "hipMalloc") &&
+            try_hip(dmalloc(&g->band_edge_f, (size_t)g->n_bands), "hipMalloc");
   if (ok)
     ok = try_hip(hipMemcpyAsync(d_sig, sig.data(), sizeof(double) * sig.size(), hipMemcpyHostToDevice, st), "H2D") &&
          try_hip(hipMemcpyAsync(d_vk, vk.data(), sizeof(int32_t) * vk.size(), hipMemcpyHostToDevice, st), "H2D") &&
          try_hip(hipMemcpyAsync(g->ch, cd.data(), sizeof(ChanDev) * cd.size(), hipMemcpyHostToDevice, st), "H2D") &&
+         try_hip(hipMemcpyAsync(g->ch_f, cf.data(), sizeof(ChanP<float>) * cf.size(), hipMemcpyHostToDevice, st), "H2D") &&
          try_hip(launch_build_rates(d_sig, d_vk, n_channels, n_bins, e_max_eV, density_cm3, k_a(), g->cum,
                                     g->total, d_binmax, st), "rate-table kernels") &&
          try_hip(launch_build_bands(d_binmax, n_bins, band_bins, g->n_bands, e_max_eV, g->band_gamma,
-                                    g->band_inv, g->band_edge, d_gamma, st), "band kernels");
+                                    g->band_inv, g->band_edge, d_gamma, st), "band kernels") &&
+         // cumulative column 0, contiguous (staged in LDS by the transport)
+         try_hip(hipMemcpy2DAsync(g->cum0, sizeof(double), g->cum, sizeof(double) * n_channels,
+                                  sizeof(double), nn, hipMemcpyDeviceToDevice, st), "column copy") &&
+         try_hip(launch_tables_f32(g->cum, g->total, g->cum0, nn * n_channels, (int)nn, g->band_gamma,
+                                   g->band_edge, g->n_bands, g->cum_f, g->total_f, g->cum0_f,
+                                   g->band_gamma_f, g->band_inv_f, g->band_edge_f, st), "FP32 tables");
   double gamma = 0.0;
   if (ok)
     ok = try_hip(hipMemcpyAsync(&gamma, d_gamma, sizeof(double), hipMemcpyDeviceToHost, st), "D2H") &&
@@ -250,6 +292,7 @@ avm_status avm_gas_create(int32_t device, double e_max_eV, int32_t n_bins, doubl
   g->gamma = gamma;
   GasDev& D = g->dev;
   D.cum = g->cum;
+  D.cum0 = g->cum0;
   D.total = g->total;
   D.band_gamma = g->band_gamma;
   D.band_inv = g->band_inv;
@@ -263,6 +306,21 @@ avm_status avm_gas_create(int32_t device, double e_max_eV, int32_t n_bins, doubl
   D.n_ch = n_channels;
   D.n_bands = g->n_bands;
   D.band_bins = band_bins;
+  D.ch0 = cd[0];
+  D.cum_f = g->cum_f;
+  D.cum0_f = g->cum0_f;
+  D.total_f = g->total_f;
+  D.band_gamma_f = g->band_gamma_f;
+  D.band_inv_f = g->band_inv_f;
+  D.band_edge_f = g->band_edge_f;
+  D.ch_f = g->ch_f;
+  D.ch0_f = cf[0];
+  float gf = (float)gamma;
+  if ((double)gf < gamma) gf = std::nextafter(gf, INFINITY);  // a majorant stays a majorant
+  D.gamma_f = gf;
+  D.inv_gamma_f = 1.0f / gf;
+  D.scale_f = (float)D.scale;
+  D.band_scale_f = (float)D.band_scale;
   *out = g;
   return AVM_OK;
 }
@@ -433,6 +491,8 @@ static void run_free(avm_run* r) {
   if (r->ev0) (void)hipEventDestroy(r->ev0);
   if (r->ev1) (void)hipEventDestroy(r->ev1);
   if (r->ev_done) (void)hipEventDestroy(r->ev_done);
+  if (r->graph_exec) (void)hipGraphExecDestroy(r->graph_exec);
+  if (r->graph) (void)hipGraphDestroy(r->graph);
   delete r;
 }
 
@@ -446,7 +506,7 @@ static size_t layout_store(Store& S, char* base, uint64_t cap) {
   };
   take(&S.x0, 8); take(&S.y0, 8); take(&S.z0, 8); take(&S.t0, 8);
   take(&S.vx0, 8); take(&S.vy0, 8); take(&S.vz0, 8); take(&S.e0, 8);
-  take(&S.eid, 8); take(&S.parent, 8); take(&S.aval, 4); take(&S.ready, 4);
+  take(&S.eid, 8); take(&S.parent, 8); take(&S.aval, 4); take(&S.qready, 4); take(&S.qslot, 4);
   take(&S.x1, 8); take(&S.y1, 8); take(&S.z1, 8); take(&S.t1, 8); take(&S.e1, 8);
   take(&S.vx1, 8); take(&S.vy1, 8); take(&S.vz1, 8);
   take(&S.k1, 4); take(&S.band1, 4);
@@ -470,7 +530,6 @@ avm_status avm_run_create(const avm_gas* gas, const avm_field* field, const avm_
     return fail(AVM_E_ARG, "avm_run_create: %u avalanches but %u field vectors", n_aval, field->dev.n_E);
   avm_run_opts o = *opts;
   if (o.precision != AVM_FP64 && o.precision != AVM_FP32_MIXED) return fail(AVM_E_ARG, "avm_run_create: bad precision");
-  if (o.precision == AVM_FP32_MIXED) return fail(AVM_E_UNSUPPORTED, "avm_run_create: FP32-mixed precision is not built");
   if (o.mode != AVM_MODE_PLAIN && o.mode != AVM_MODE_BATCHED) return fail(AVM_E_ARG, "avm_run_create: bad mode");
   if (o.majorant != AVM_MAJORANT_GLOBAL && o.majorant != AVM_MAJORANT_BANDED) return fail(AVM_E_ARG, "avm_run_create: bad majorant");
   if (o.majorant == AVM_MAJORANT_BANDED && gas->n_bands < 2)
@@ -483,8 +542,10 @@ avm_status avm_run_create(const avm_gas* gas, const avm_field* field, const avm_
   if (o.capacity == 0) o.capacity = n_prim * 64 > (1u << 20) ? n_prim * 64 : (1u << 20);
   if (o.capacity < n_prim) return fail(AVM_E_ARG, "avm_run_create: capacity %llu < %llu primaries", (unsigned long long)o.capacity, (unsigned long long)n_prim);
   if (o.capacity > 0xFFFFFFF0ull) return fail(AVM_E_ARG, "avm_run_create: capacity above 2^32-16");
-  if (o.flights_per_pass <= 0) o.flights_per_pass = 32;
+  if (o.flights_per_pass <= 0) o.flights_per_pass = 64;
   if (o.waves_per_cu < 0) return fail(AVM_E_ARG, "avm_run_create: waves_per_cu < 0");
+  if (o.graph && o.mode != AVM_MODE_BATCHED)
+    return fail(AVM_E_ARG, "avm_run_create: graph capture needs the batched mode (the plain mode reads the host)");
   if (!prim_on_device)
     for (uint64_t i = 0; i < n_prim; ++i) {
       const avm_primary& p = prim[i];
@@ -508,10 +569,11 @@ avm_status avm_run_create(const avm_gas* gas, const avm_field* field, const avm_
   const size_t bytes = layout_store(r->S, nullptr, cap);
   hipError_t e = hipMalloc(&r->store_mem, bytes);
   if (e == hipSuccess) layout_store(r->S, static_cast<char*>(r->store_mem), cap);
-  if (e == hipSuccess) e = hipMemset(r->S.ready, 0, sizeof(uint32_t) * cap);
+  if (e == hipSuccess) e = hipMemset(r->S.qready, 0, sizeof(uint32_t) * cap);
   if (e == hipSuccess && o.mode == AVM_MODE_PLAIN) e = dmalloc(&r->list0, cap);
   if (e == hipSuccess && o.mode == AVM_MODE_PLAIN) e = dmalloc(&r->list1, cap);
   if (e == hipSuccess) e = dmalloc(&r->ctr, 1);
+  if (e == hipSuccess) e = hipMemset(r->ctr, 0, sizeof(Counters));
   if (e == hipSuccess) e = dmalloc(&r->stats, n_aval ? n_aval : 1);
   if (e == hipSuccess) e = dmalloc(&r->tot, 1);
   if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&r->tot_host), sizeof(Totals), hipHostMallocDefault);
@@ -532,7 +594,8 @@ avm_status avm_run_create(const avm_gas* gas, const avm_field* field, const avm_
   if (e == hipSuccess) e = hipEventCreateWithFlags(&r->ev_done, hipEventDisableTiming);
   if (e == hipSuccess && o.mode == AVM_MODE_BATCHED) {
     int per_cu = 0, n_cu = 0, dev = 0;
-    e = persistent_occupancy(o.majorant == AVM_MAJORANT_BANDED, field->dev.kind, r->block, &per_cu);
+    e = persistent_occupancy(o.precision == AVM_FP32_MIXED, o.majorant == AVM_MAJORANT_BANDED,
+                             field->dev.kind, r->block, &per_cu);
     if (e == hipSuccess) e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
     if (e == hipSuccess) {
@@ -565,6 +628,9 @@ static RunParams run_params(const avm_run* r) {
   P.k_a = k_a();
   P.two_ka = 2.0 * P.k_a;
   P.inv_2ka = 1.0 / P.two_ka;
+  P.k_a_f = (float)P.k_a;
+  P.two_ka_f = (float)P.two_ka;
+  P.inv_2ka_f = (float)P.inv_2ka;
   // device time budget of one transport kernel: the caller's timeout, else
   // a hard cap; a kernel past it stops and the run reports AVM_E_TIMEOUT
   const double budget_s = r->opts.timeout_s > 0.0 ? r->opts.timeout_s : 600.0;
@@ -572,57 +638,100 @@ static RunParams run_params(const avm_run* r) {
   return P;
 }
 
-avm_status avm_run_execute(avm_run* r) {
-  g_err.clear();
-  if (!r) return fail(AVM_E_ARG, "avm_run_execute: run is NULL");
-  DeviceGuard dg(r->gas->device);
-  hipStream_t st = r->stream;
-  r->epoch += 1;
-  if (r->epoch == 0) r->epoch = 1;
-  r->executed = 1;
-  r->synced = 0;
+// The batched run's device work, in stream order: primaries (if on the
+// host), reset, primary load, persistent transport, statistics, result copies.
+static avm_status enqueue_batched(avm_run* r, hipStream_t st, bool timed) {
   const PrimaryRec* pd = r->prim_dev_user;
   if (!r->prim_on_device && r->n_prim) {
     HIP_TRY(hipMemcpyAsync(r->prim_dev, r->prim_host, sizeof(PrimaryRec) * r->n_prim, hipMemcpyHostToDevice, st));
     pd = r->prim_dev;
   }
-  const int plain = r->opts.mode == AVM_MODE_PLAIN;
   HIP_TRY(launch_reset(r->ctr, r->n_prim, r->stats, r->n_aval, r->tot, st));
-  HIP_TRY(launch_load_primaries(pd, r->n_prim, r->S, r->epoch, k_a(), r->n_aval, r->list0, r->ctr, plain, st));
+  HIP_TRY(launch_load_primaries(pd, r->n_prim, r->S, k_a(), r->n_aval, r->list0, r->ctr, 0, st));
+  const RunParams P = run_params(r);
+  if (timed) HIP_TRY(hipEventRecord(r->ev0, st));
+  HIP_TRY(launch_persistent(r->opts.precision == AVM_FP32_MIXED, r->opts.majorant == AVM_MAJORANT_BANDED,
+                            r->field->dev.kind, r->gas->dev, r->field->dev, P, r->S, r->ctr,
+                            r->opts.flights_per_pass, r->grid, r->block, st));
+  if (timed) HIP_TRY(hipEventRecord(r->ev1, st));
+  HIP_TRY(launch_stats(r->S, r->ctr, r->stats, r->tot, st));
+  HIP_TRY(hipMemcpyAsync(r->tot_host, r->tot, sizeof(Totals), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(r->ctr_host, r->ctr, sizeof(Counters), hipMemcpyDeviceToHost, st));
+  return AVM_OK;
+}
+
+avm_status avm_run_execute(avm_run* r) {
+  g_err.clear();
+  if (!r) return fail(AVM_E_ARG, "avm_run_execute: run is NULL");
+  DeviceGuard dg(r->gas->device);
+  hipStream_t st = r->stream;
+  r->executed = 1;
+  r->synced = 0;
+  if (r->opts.mode == AVM_MODE_BATCHED) {
+    if (!r->opts.graph) {
+      avm_status s = enqueue_batched(r, st, true);
+      if (s != AVM_OK) return s;
+    } else {
+      if (!r->graph_exec) {
+        // capture once on a private stream, replay on the run's stream
+        hipStream_t cs = nullptr;
+        HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+        hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        avm_status s = e == hipSuccess ? enqueue_batched(r, cs, false) : AVM_E_HIP;
+        hipGraph_t g = nullptr;
+        const hipError_t e2 = hipStreamEndCapture(cs, &g);
+        (void)hipStreamDestroy(cs);
+        if (e != hipSuccess) return fail(AVM_E_HIP, "hipStreamBeginCapture: %s", hipGetErrorString(e));
+        if (s != AVM_OK) {
+          if (g) (void)hipGraphDestroy(g);
+          return s;
+        }
+        if (e2 != hipSuccess) return fail(AVM_E_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e2));
+        r->graph = g;
+        HIP_TRY(hipGraphInstantiate(&r->graph_exec, g, nullptr, nullptr, 0));
+      }
+      HIP_TRY(hipEventRecord(r->ev0, st));
+      HIP_TRY(hipGraphLaunch(r->graph_exec, st));
+      HIP_TRY(hipEventRecord(r->ev1, st));
+    }
+    r->iterations = 1;
+    HIP_TRY(hipEventRecord(r->ev_done, st));
+    return AVM_OK;
+  }
+  // plain mode: the paper's loop -- transport every active electron to its
+  // next ionisation or termination, then rebuild the active list, until
+  // none is left; the host reads the list size after each iteration
+  const PrimaryRec* pd = r->prim_dev_user;
+  if (!r->prim_on_device && r->n_prim) {
+    HIP_TRY(hipMemcpyAsync(r->prim_dev, r->prim_host, sizeof(PrimaryRec) * r->n_prim, hipMemcpyHostToDevice, st));
+    pd = r->prim_dev;
+  }
+  HIP_TRY(launch_reset(r->ctr, r->n_prim, r->stats, r->n_aval, r->tot, st));
+  HIP_TRY(launch_load_primaries(pd, r->n_prim, r->S, k_a(), r->n_aval, r->list0, r->ctr, 1, st));
   const RunParams P = run_params(r);
   const int banded = r->opts.majorant == AVM_MAJORANT_BANDED;
   const int fk = r->field->dev.kind;
-  if (plain) {
-    // the paper's loop: transport every active electron to its next
-    // ionisation or termination, then rebuild the active list, until none
-    // is left; the host reads the list size after each iteration
-    uint64_t n_active = r->n_prim;
-    uint32_t *A = r->list0, *B = r->list1;
-    r->iterations = 0;
-    r->plain_ms = 0.0;
-    while (n_active > 0) {
-      HIP_TRY(hipMemsetAsync(&r->ctr->next, 0, sizeof(unsigned long long), st));
-      HIP_TRY(hipEventRecord(r->ev0, st));
-      HIP_TRY(launch_generation(banded, fk, r->gas->dev, r->field->dev, P, r->S, A, (uint32_t)n_active, B, r->ctr, st));
-      HIP_TRY(hipEventRecord(r->ev1, st));
-      HIP_TRY(hipMemcpyAsync(r->ctr_host, r->ctr, sizeof(Counters), hipMemcpyDeviceToHost, st));
-      HIP_TRY(hipStreamSynchronize(st));
-      float ms = 0.f;
-      HIP_TRY(hipEventElapsedTime(&ms, r->ev0, r->ev1));
-      r->plain_ms += ms;
-      r->iterations += 1;
-      n_active = r->ctr_host->next;
-      if (r->ctr_host->timeout) break;
-      uint32_t* t = A;
-      A = B;
-      B = t;
-    }
-  } else {
+  const int fp32 = r->opts.precision == AVM_FP32_MIXED;
+  uint64_t n_active = r->n_prim;
+  uint32_t *A = r->list0, *B = r->list1;
+  r->iterations = 0;
+  r->plain_ms = 0.0;
+  while (n_active > 0) {
+    HIP_TRY(hipMemsetAsync(&r->ctr->next, 0, sizeof(unsigned long long), st));
     HIP_TRY(hipEventRecord(r->ev0, st));
-    HIP_TRY(launch_persistent(banded, fk, r->gas->dev, r->field->dev, P, r->S, r->ctr, r->epoch,
-                              r->opts.flights_per_pass, r->grid, r->block, st));
+    HIP_TRY(launch_generation(fp32, banded, fk, r->gas->dev, r->field->dev, P, r->S, A, (uint32_t)n_active, B, r->ctr, st));
     HIP_TRY(hipEventRecord(r->ev1, st));
-    r->iterations = 1;
+    HIP_TRY(hipMemcpyAsync(r->ctr_host, r->ctr, sizeof(Counters), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, r->ev0, r->ev1));
+    r->plain_ms += ms;
+    r->iterations += 1;
+    n_active = r->ctr_host->next;
+    if (r->ctr_host->timeout) break;
+    uint32_t* t = A;
+    A = B;
+    B = t;
   }
   HIP_TRY(launch_stats(r->S, r->ctr, r->stats, r->tot, st));
   HIP_TRY(hipMemcpyAsync(r->tot_host, r->tot, sizeof(Totals), hipMemcpyDeviceToHost, st));

@@ -15,6 +15,16 @@
 // k = flight index of the electron, j = block within the event (0 flight,
 // 1 scattering, 2-3 ionisation): results do not depend on which lane, wave
 // or kernel carries an electron.
+//
+// Precision is a template parameter R of the step:
+//   R = double: FP64 throughout (53-bit uniforms);
+//   R = float : FP32-mixed -- velocities, flight times, energies, table
+//               interpolation and scattering in FP32 (24-bit uniforms from the
+//               high word of the same Philox output, so an FP32 run and an
+//               FP64 run see common random numbers); position and time are
+//               accumulated in FP64; boundary crossings are solved in FP64;
+//               a collision decision whose FP32 margin is below 2^-18 is
+//               taken again in FP64.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -38,30 +48,62 @@ enum : uint32_t {
 };
 enum : int32_t { CH_ELASTIC = 0, CH_EXCITATION = 1, CH_IONISATION = 2, CH_ATTACHMENT = 3 };
 
-// Per-channel scattering parameters (device copy, read on real collisions).
-struct ChanDev {
+// Per-channel scattering parameters, in the step's precision R.
+template <class R>
+struct ChanP {
   int32_t kind, angular, split, _pad;
-  double loss, e_lo, e_hi;
-  double mu;            // m/M
-  double el_loss;       // 2 mu / (1 + mu)^2
-  double mu2p1;         // 1 + mu^2
-  double two_mu;        // 2 mu
-  double split_w;       // Opal-Beaty w
-  double atan_scale;    // 1 / (2 w)
-  double inv_screen8;   // 8 / screening (1/eta = 8 e / screening)
+  double e_lo, e_hi;    // validity window (compared in FP64)
+  R loss;
+  R mu;                 // m/M
+  R el_loss;            // 2 mu / (1 + mu)^2
+  R mu2p1;              // 1 + mu^2
+  R two_mu;             // 2 mu
+  R split_w;            // Opal-Beaty w
+  R atan_scale;         // 1 / (2 w)
+  R inv_screen8;        // 8 / screening (1/eta = 8 e / screening)
 };
+using ChanDev = ChanP<double>;
 
+// Rate tables of one gas on the device.  FP64 tables serve the FP64 path and
+// the FP64 re-evaluation of close FP32 decisions; FP32 copies serve the
+// FP32-mixed path (majorants rounded up, band edges rounded down, so the
+// FP32 bounds stay bounds).
 struct GasDev {
   const double* cum;        // [(n_bins+1) * n_ch] node-major cumulative rates, 1/ns
+  const double* cum0;       // [n_bins+1] cumulative column 0 (the first channel's rate)
   const double* total;      // [n_bins+1] total rate at the nodes
   const double* band_gamma; // [n_bands]
   const double* band_inv;   // [n_bands] 1 / Gamma_b
   const double* band_edge;  // [n_bands] upper edge (eV), +inf for the last
   const ChanDev* ch;        // [n_ch]
+  const float* cum_f;       // FP32 copies of the above
+  const float* cum0_f;
+  const float* total_f;
+  const float* band_gamma_f;
+  const float* band_inv_f;
+  const float* band_edge_f;
+  const ChanP<float>* ch_f;
   double scale;             // n_bins / E_max
   double gamma, inv_gamma;
   double band_scale;        // n_bins / (E_max * band_bins): first guess of the band
+  float gamma_f, inv_gamma_f, scale_f, band_scale_f;
   int32_t n_bins, n_ch, n_bands, band_bins;
+  ChanDev ch0;              // channel 0 by value (kernel argument: scalar registers)
+  ChanP<float> ch0_f;
+};
+
+// Where the hot tables are read from: `tot` and `cum0` hold nodes
+// [0, n_lo) of the total rate and of cumulative column 0 (LDS copies in the
+// persistent kernel, the global arrays elsewhere); band tables likewise.
+// Both sources hold the same values, so results do not depend on the view.
+template <class R>
+struct TabView {
+  const R* tot;
+  const R* cum0;
+  int32_t n_lo;
+  const R* bgam;
+  const R* binv;
+  const R* bedge;
 };
 
 enum FieldKind : int32_t { FIELD_SLAB = 0, FIELD_POLAR = 1 };
@@ -91,16 +133,16 @@ struct RunParams {
   int32_t banded;
   double t_max;
   double k_a, two_ka, inv_2ka;
+  float k_a_f, two_ka_f, inv_2ka_f, _padf;
   uint64_t budget_ticks;    // wall_clock64() ticks a transport kernel may run
 };
 
 // ---------------------------------------------------------------------------
-// Philox4x32-10
+// Philox4x32-10 and uniform maps
 // ---------------------------------------------------------------------------
 struct Block { uint32_t w0, w1, w2, w3; };
 
-AVM_FN Block philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
-                                        uint32_t k0, uint32_t k1) {
+AVM_FN Block philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1) {
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
     const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
@@ -116,8 +158,7 @@ AVM_FN Block philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
   return Block{c0, c1, c2, c3};
 }
 
-AVM_FN Block draw(const RunParams& p, uint32_t aval, uint64_t eid, uint32_t k,
-                                      uint32_t j) {
+AVM_FN Block draw(const RunParams& p, uint32_t aval, uint64_t eid, uint32_t k, uint32_t j) {
   return philox(4u * k + j, aval, (uint32_t)eid, (uint32_t)(eid >> 32), p.key0, p.key1);
 }
 
@@ -127,57 +168,101 @@ AVM_FN double u53(uint32_t hi, uint32_t lo) {
   return __builtin_fma((double)(hi >> 5), 67108864.0, (double)((lo >> 6) + 1u)) *
          1.1102230246251565e-16;
 }
+// 24-bit uniform in (0, 1] from the high word alone, exact in binary32.
+AVM_FN float u24(uint32_t hi) { return (float)((hi >> 8) + 1u) * 5.9604644775390625e-8f; }
 
 // ---------------------------------------------------------------------------
-// geometry helpers
+// precision-generic arithmetic
 // ---------------------------------------------------------------------------
-AVM_FN double dot3(double ax, double ay, double az, double bx, double by,
-                                       double bz) {
-  return ax * bx + ay * by + az * bz;
+template <class R> struct M;
+template <> struct M<double> {
+  AVM_FN static double uni(uint32_t hi, uint32_t lo) { return u53(hi, lo); }
+  AVM_FN static double fma(double a, double b, double c) { return __builtin_fma(a, b, c); }
+  AVM_FN static double sqrt_(double x) { return sqrt(x); }
+  AVM_FN static double rsqrt_(double x) { return rsqrt(x); }
+  AVM_FN static double log_(double x) { return log(x); }
+  AVM_FN static double floor_(double x) { return floor(x); }
+  AVM_FN static double tan_(double x) { return tan(x); }
+  AVM_FN static double atan_(double x) { return atan(x); }
+  AVM_FN static void sincospi_(double x, double* s, double* c) { sincospi(x, s, c); }
+  AVM_FN static void sincos_(double x, double* s, double* c) { sincos(x, s, c); }
+  AVM_FN static double sin_(double x) { return sin(x); }
+  AVM_FN static double abs_(double x) { return fabs(x); }
+  AVM_FN static double inf() { return __builtin_inf(); }
+};
+template <> struct M<float> {
+  AVM_FN static float uni(uint32_t hi, uint32_t) { return u24(hi); }
+  AVM_FN static float fma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+  AVM_FN static float sqrt_(float x) { return sqrtf(x); }
+  AVM_FN static float rsqrt_(float x) { return rsqrtf(x); }
+  AVM_FN static float log_(float x) { return logf(x); }
+  AVM_FN static float floor_(float x) { return floorf(x); }
+  AVM_FN static float tan_(float x) { return tanf(x); }
+  AVM_FN static float atan_(float x) { return atanf(x); }
+  AVM_FN static void sincospi_(float x, float* s, float* c) { sincospif(x, s, c); }
+  AVM_FN static void sincos_(float x, float* s, float* c) { sincosf(x, s, c); }
+  AVM_FN static float sin_(float x) { return sinf(x); }
+  AVM_FN static float abs_(float x) { return fabsf(x); }
+  AVM_FN static float inf() { return __builtin_inff(); }
+};
+
+template <class R>
+AVM_FN R dot3(R ax, R ay, R az, R bx, R by, R bz) {
+  return M<R>::fma(az, bz, M<R>::fma(ay, by, ax * bx));
 }
 
-// Direction of (vx, vy, vz) turned by polar angle theta (cos_t) and azimuth
-// phi.  The transverse length s = sqrt(dx^2 + dy^2) avoids the cancellation
-// of sqrt(1 - dz^2) next to the poles, so |d'| = 1 to rounding.
-AVM_FN void turn(double dx, double dy, double dz, double cos_t, double phi,
-                                     double& ox, double& oy, double& oz) {
-  const double st2 = 1.0 - cos_t * cos_t;
-  const double sin_t = st2 > 0.0 ? sqrt(st2) : 0.0;
-  double sp, cp;
-  sincos(phi, &sp, &cp);
-  const double s = sqrt(dx * dx + dy * dy);
-  if (s > 1e-12) {
-    const double inv_s = 1.0 / s;
-    ox = dx * cos_t + sin_t * (dx * dz * cp - dy * sp) * inv_s;
-    oy = dy * cos_t + sin_t * (dy * dz * cp + dx * sp) * inv_s;
-    oz = dz * cos_t - s * sin_t * cp;
+// Interpolation (1-f) a + f b with non-negative weights: monotone in a and
+// b after rounding, so interpolated cumulative rates stay ordered.
+template <class R>
+AVM_FN R lerp(R a, R b, R g1, R f) { return M<R>::fma(f, b, g1 * a); }
+
+// Direction of (dx, dy, dz) turned by polar angle theta (cos_t) and azimuth
+// phi = 2 pi u_phi (sin and cos from sincospi, no general argument
+// reduction).  The transverse length s = sqrt(dx^2 + dy^2) avoids the
+// cancellation of sqrt(1 - dz^2) next to the poles, so |d'| = 1 to rounding.
+template <class R>
+AVM_FN void turn(R dx, R dy, R dz, R cos_t, R u_phi, R& ox, R& oy, R& oz) {
+  const R st2 = M<R>::fma(-cos_t, cos_t, R(1));
+  const R sin_t = st2 > R(0) ? M<R>::sqrt_(st2) : R(0);
+  R sp, cp;
+  M<R>::sincospi_(R(2) * u_phi, &sp, &cp);
+  const R q = M<R>::fma(dx, dx, dy * dy);
+  const R tiny = sizeof(R) == 8 ? R(1e-24) : R(1e-12);
+  if (q > tiny) {
+    const R inv_s = M<R>::rsqrt_(q);
+    const R s = q * inv_s;
+    const R a = sin_t * inv_s;
+    ox = M<R>::fma(dx, cos_t, a * M<R>::fma(dx * dz, cp, -dy * sp));
+    oy = M<R>::fma(dy, cos_t, a * M<R>::fma(dy * dz, cp, dx * sp));
+    oz = M<R>::fma(dz, cos_t, -s * sin_t * cp);
   } else {
     ox = sin_t * cp;
     oy = sin_t * sp;
-    oz = (dz < 0.0 ? -1.0 : 1.0) * cos_t;
+    oz = (dz < R(0) ? R(-1) : R(1)) * cos_t;
   }
 }
 
 // Real roots of A s^2 + B s + C = 0 in ascending order (stable form).
-AVM_FN int roots2(double A, double B, double C, double& r1, double& r2) {
-  if (A == 0.0) {
-    if (B == 0.0) return 0;
+template <class R>
+AVM_FN int roots2(R A, R B, R C, R& r1, R& r2) {
+  if (A == R(0)) {
+    if (B == R(0)) return 0;
     r1 = -C / B;
     return 1;
   }
-  const double disc = B * B - 4.0 * A * C;
-  if (disc < 0.0) return 0;
-  const double sq = sqrt(disc);
-  const double q = -0.5 * (B + (B >= 0.0 ? sq : -sq));
-  if (q == 0.0) {
-    r1 = 0.0;
-    r2 = 0.0;
+  const R disc = B * B - R(4) * A * C;
+  if (disc < R(0)) return 0;
+  const R sq = M<R>::sqrt_(disc);
+  const R q = R(-0.5) * (B + (B >= R(0) ? sq : -sq));
+  if (q == R(0)) {
+    r1 = R(0);
+    r2 = R(0);
   } else {
     r1 = q / A;
     r2 = C / q;
   }
   if (r1 > r2) {
-    const double t = r1;
+    const R t = r1;
     r1 = r2;
     r2 = t;
   }
@@ -188,19 +273,17 @@ AVM_FN int roots2(double A, double B, double C, double& r1, double& r2) {
 // [zlo, zhi): arrival at zhi, or a crossing below zlo with dz/ds < 0 (s = 0
 // counts when sitting on zlo moving down).  A cheap bound on the extremes of
 // the parabola over [0, T] rules out the common no-exit case before any root
-// is taken.
-AVM_FN uint32_t slab_exit(double z0, double vz, double az, double zlo,
-                                              double zhi, double T, double& s_exit) {
-  const double zT = z0 + vz * T + 0.5 * az * T * T;
+// is taken.  FP64 in both precisions.
+AVM_FN uint32_t slab_exit(double z0, double vz, double az, double zlo, double zhi, double T,
+                          double& s_exit) {
+  const double zT = __builtin_fma(0.5 * az * T, T, __builtin_fma(vz, T, z0));
   double zmin = z0 < zT ? z0 : zT;
   double zmax = z0 > zT ? z0 : zT;
-  if (az != 0.0) {
-    const double sv = -vz / az;  // vertex
-    if (sv > 0.0 && sv < T) {
-      const double zv = z0 + vz * sv + 0.5 * az * sv * sv;
-      zmin = zmin < zv ? zmin : zv;
-      zmax = zmax > zv ? zmax : zv;
-    }
+  // the vertex s* = -vz/az lies in (0, T) iff vz az < 0 and |vz| < |az| T
+  if (vz * az < 0.0 && fabs(vz) < fabs(az) * T) {
+    const double zv = z0 - 0.5 * vz * vz / az;
+    zmin = zmin < zv ? zmin : zv;
+    zmax = zmax > zv ? zmax : zv;
   }
   // margin: a relative 1e-12 of the coordinates keeps the filter conservative
   const double m = 1e-12 * (fabs(z0) + fabs(zhi) + fabs(zlo) + fabs(vz * T) + fabs(az * T * T));
@@ -208,7 +291,7 @@ AVM_FN uint32_t slab_exit(double z0, double vz, double az, double zlo,
   double best = __builtin_inf();
   uint32_t side = 0;
   double r1 = 0.0, r2 = 0.0;
-  int n = roots2(0.5 * az, vz, z0 - zhi, r1, r2);
+  int n = roots2<double>(0.5 * az, vz, z0 - zhi, r1, r2);
   if (n >= 1 && r1 > 0.0) {
     best = r1;
     side = ST_HIGH;
@@ -216,7 +299,7 @@ AVM_FN uint32_t slab_exit(double z0, double vz, double az, double zlo,
     best = r2;
     side = ST_HIGH;
   }
-  n = roots2(0.5 * az, vz, z0 - zlo, r1, r2);
+  n = roots2<double>(0.5 * az, vz, z0 - zlo, r1, r2);
   for (int i = 0; i < n; ++i) {
     const double s = i == 0 ? r1 : r2;
     if (s < 0.0) continue;
@@ -239,12 +322,14 @@ AVM_FN uint32_t slab_exit(double z0, double vz, double az, double zlo,
 // ---------------------------------------------------------------------------
 // fields
 // ---------------------------------------------------------------------------
-AVM_FN void polar_field(const FieldDev& F, double x, double y, double& Ex,
-                                            double& Ey) {
+// Polar map: bilinear in (ln rho, phi), clamped in rho, periodic in phi,
+// rotated to Cartesian.
+template <class R>
+AVM_FN void polar_field(const FieldDev& F, double x, double y, R& Ex, R& Ey) {
   const double rho = sqrt(x * x + y * y);
   if (!(rho > 0.0)) {
-    Ex = 0.0;
-    Ey = 0.0;
+    Ex = R(0);
+    Ey = R(0);
     return;
   }
   double u = (log(rho) - F.ln_a) * F.inv_dlog;
@@ -252,26 +337,26 @@ AVM_FN void polar_field(const FieldDev& F, double x, double y, double& Ex,
   u = u < 0.0 ? 0.0 : (u > umax ? umax : u);
   int i = (int)floor(u);
   i = i > F.n_r - 2 ? F.n_r - 2 : i;
-  const double fr = u - (double)i;
+  const R fr = (R)(u - (double)i);
   double phi = atan2(y, x);
   if (phi < 0.0) phi += 6.283185307179586;
   const double w = phi * (0.15915494309189535 * (double)F.n_phi);
   const double wf = floor(w);
-  const double fp = w - wf;
+  const R fp = (R)(w - wf);
   int j0 = (int)wf;
   j0 = j0 >= F.n_phi ? j0 - F.n_phi : j0;
   const int j1 = j0 + 1 == F.n_phi ? 0 : j0 + 1;
   const int np = F.n_phi;
-  const double w00 = (1.0 - fr) * (1.0 - fp), w01 = (1.0 - fr) * fp;
-  const double w10 = fr * (1.0 - fp), w11 = fr * fp;
-  const float* R = F.Er;
-  const float* P = F.Ephi;
-  const double er = w00 * (double)R[i * np + j0] + w01 * (double)R[i * np + j1] +
-                    w10 * (double)R[(i + 1) * np + j0] + w11 * (double)R[(i + 1) * np + j1];
-  const double ep = w00 * (double)P[i * np + j0] + w01 * (double)P[i * np + j1] +
-                    w10 * (double)P[(i + 1) * np + j0] + w11 * (double)P[(i + 1) * np + j1];
+  const R w00 = (R(1) - fr) * (R(1) - fp), w01 = (R(1) - fr) * fp;
+  const R w10 = fr * (R(1) - fp), w11 = fr * fp;
+  const float* A = F.Er;
+  const float* B = F.Ephi;
+  const R er = w00 * (R)A[i * np + j0] + w01 * (R)A[i * np + j1] + w10 * (R)A[(i + 1) * np + j0] +
+               w11 * (R)A[(i + 1) * np + j1];
+  const R ep = w00 * (R)B[i * np + j0] + w01 * (R)B[i * np + j1] + w10 * (R)B[(i + 1) * np + j0] +
+               w11 * (R)B[(i + 1) * np + j1];
   const double inv = 1.0 / rho;
-  const double c = x * inv, s = y * inv;
+  const R c = (R)(x * inv), s = (R)(y * inv);
   Ex = er * c - ep * s;
   Ey = er * s + ep * c;
 }
@@ -279,31 +364,79 @@ AVM_FN void polar_field(const FieldDev& F, double x, double y, double& Ex,
 // ---------------------------------------------------------------------------
 // electron state and one pass of the transport loop
 // ---------------------------------------------------------------------------
+template <class R>
 struct Elec {
-  double x, y, z, t, vx, vy, vz;
+  double x, y, z, t;  // accumulators: FP64 in both precisions
+  R vx, vy, vz;
   uint64_t eid;
   uint32_t aval, k;
   int32_t band;
   uint32_t n_real, n_ion, n_null, n_masked, n_band, n_over;
-  double Ex, Ey, Ez;  // slab: the avalanche's field, loaded once per electron
+  R Ex, Ey, Ez;  // slab: the avalanche's field, loaded once per electron
 };
 
+template <class R>
 struct Child {
-  double vx, vy, vz, e;
+  R vx, vy, vz, e;
   uint64_t eid;
+  R pen;      // pending ionisation: energy at the collision
+  int32_t pc; // pending ionisation: channel
 };
 
 enum : int32_t { STEP_CONTINUE = 0, STEP_IONISED = 1, STEP_DONE = 2 };
 
-AVM_FN int32_t band_of(const GasDev& G, double e) {
-  int32_t b = (int32_t)(e * G.band_scale);
+// Precision-selected members of the gas and run parameters.
+template <class R> struct Sel;
+template <> struct Sel<double> {
+  AVM_FN static double scale(const GasDev& G) { return G.scale; }
+  AVM_FN static double band_scale(const GasDev& G) { return G.band_scale; }
+  AVM_FN static double gamma(const GasDev& G) { return G.gamma; }
+  AVM_FN static double inv_gamma(const GasDev& G) { return G.inv_gamma; }
+  AVM_FN static const ChanP<double>& ch0(const GasDev& G) { return G.ch0; }
+  AVM_FN static const ChanP<double>* ch(const GasDev& G) { return G.ch; }
+  AVM_FN static const double* total(const GasDev& G) { return G.total; }
+  AVM_FN static const double* cum0(const GasDev& G) { return G.cum0; }
+  AVM_FN static const double* cum(const GasDev& G) { return G.cum; }
+  AVM_FN static double k_a(const RunParams& P) { return P.k_a; }
+  AVM_FN static double two_ka(const RunParams& P) { return P.two_ka; }
+  AVM_FN static double inv_2ka(const RunParams& P) { return P.inv_2ka; }
+};
+template <> struct Sel<float> {
+  AVM_FN static float scale(const GasDev& G) { return G.scale_f; }
+  AVM_FN static float band_scale(const GasDev& G) { return G.band_scale_f; }
+  AVM_FN static float gamma(const GasDev& G) { return G.gamma_f; }
+  AVM_FN static float inv_gamma(const GasDev& G) { return G.inv_gamma_f; }
+  AVM_FN static const ChanP<float>& ch0(const GasDev& G) { return G.ch0_f; }
+  AVM_FN static const ChanP<float>* ch(const GasDev& G) { return G.ch_f; }
+  AVM_FN static const float* total(const GasDev& G) { return G.total_f; }
+  AVM_FN static const float* cum0(const GasDev& G) { return G.cum0_f; }
+  AVM_FN static const float* cum(const GasDev& G) { return G.cum_f; }
+  AVM_FN static float k_a(const RunParams& P) { return P.k_a_f; }
+  AVM_FN static float two_ka(const RunParams& P) { return P.two_ka_f; }
+  AVM_FN static float inv_2ka(const RunParams& P) { return P.inv_2ka_f; }
+};
+
+// The global-memory tables of precision R (no LDS copies).
+template <class R> AVM_FN TabView<R> global_view(const GasDev& G);
+template <> AVM_FN TabView<double> global_view<double>(const GasDev& G) {
+  return TabView<double>{G.total, G.cum0, G.n_bins + 1, G.band_gamma, G.band_inv, G.band_edge};
+}
+template <> AVM_FN TabView<float> global_view<float>(const GasDev& G) {
+  return TabView<float>{G.total_f, G.cum0_f, G.n_bins + 1, G.band_gamma_f, G.band_inv_f,
+                        G.band_edge_f};
+}
+
+template <class R>
+AVM_FN int32_t band_of(const GasDev& G, const TabView<R>& T, R e) {
+  int32_t b = (int32_t)(e * Sel<R>::band_scale(G));
   b = b < 0 ? 0 : (b > G.n_bands - 1 ? G.n_bands - 1 : b);
-  while (b < G.n_bands - 1 && !(e < G.band_edge[b])) ++b;
-  while (b > 0 && e < G.band_edge[b - 1]) --b;
+  while (b < G.n_bands - 1 && !(e < T.bedge[b])) ++b;
+  while (b > 0 && e < T.bedge[b - 1]) --b;
   return b;
 }
 
-AVM_FN uint32_t region_status(const FieldDev& F, const Elec& e) {
+template <class R>
+AVM_FN uint32_t region_status(const FieldDev& F, const Elec<R>& e) {
   if (F.kind == FIELD_SLAB) {
     if (e.z < F.z_lo) return ST_LOW;
     if (e.z >= F.z_hi) return ST_HIGH;
@@ -315,74 +448,174 @@ AVM_FN uint32_t region_status(const FieldDev& F, const Elec& e) {
   return 0;
 }
 
-// Free flight of duration s from (r, v) with the field frozen at E.
-AVM_FN void propagate(const FieldDev& F, const RunParams& P, const Elec& e,
-                                          double ax, double ay, double az, double Ex, double Ey,
-                                          double Ez, double s, double& rx, double& ry, double& rz,
-                                          double& ux, double& uy, double& uz) {
+// Free flight of duration s from (r, v) with the field frozen at E: the
+// displacement is formed in R and added to the FP64 position.
+template <class R>
+AVM_FN void propagate(const FieldDev& F, const Elec<R>& e, R ax, R ay, R az, R Ex, R Ey, R Ez, R s,
+                      double& rx, double& ry, double& rz, R& ux, R& uy, R& uz) {
+  using Mr = M<R>;
   if (!F.has_b) {
-    const double hs2 = 0.5 * s * s;
-    rx = e.x + e.vx * s + ax * hs2;
-    ry = e.y + e.vy * s + ay * hs2;
-    rz = e.z + e.vz * s + az * hs2;
-    ux = e.vx + ax * s;
-    uy = e.vy + ay * s;
-    uz = e.vz + az * s;
+    const R hs2 = R(0.5) * s * s;
+    rx = e.x + (double)Mr::fma(ax, hs2, e.vx * s);
+    ry = e.y + (double)Mr::fma(ay, hs2, e.vy * s);
+    rz = e.z + (double)Mr::fma(az, hs2, e.vz * s);
+    ux = Mr::fma(ax, s, e.vx);
+    uy = Mr::fma(ay, s, e.vy);
+    uz = Mr::fma(az, s, e.vz);
     return;
   }
   // constant E and B: uniform acceleration along B, E x B drift plus
   // gyration across it
-  const double bx = F.bh[0], by = F.bh[1], bz = F.bh[2];
-  const double vpar = dot3(e.vx, e.vy, e.vz, bx, by, bz);
-  const double apar = dot3(ax, ay, az, bx, by, bz);
-  const double wx = F.wd_scale * (Ey * F.Bv[2] - Ez * F.Bv[1]);
-  const double wy = F.wd_scale * (Ez * F.Bv[0] - Ex * F.Bv[2]);
-  const double wz = F.wd_scale * (Ex * F.Bv[1] - Ey * F.Bv[0]);
-  const double u0x = (e.vx - vpar * bx) - wx;
-  const double u0y = (e.vy - vpar * by) - wy;
-  const double u0z = (e.vz - vpar * bz) - wz;
-  const double cx = by * u0z - bz * u0y;
-  const double cy = bz * u0x - bx * u0z;
-  const double cz = bx * u0y - by * u0x;
-  const double ph = F.omega * s;
-  double sn, cs;
-  sincos(ph, &sn, &cs);
-  const double sh = sin(0.5 * ph);
-  const double omc = 2.0 * sh * sh;
-  const double along = vpar * s + 0.5 * apar * s * s;
-  const double a1 = sn * F.inv_omega, a2 = omc * F.inv_omega;
-  rx = e.x + along * bx + wx * s + a1 * u0x + a2 * cx;
-  ry = e.y + along * by + wy * s + a1 * u0y + a2 * cy;
-  rz = e.z + along * bz + wz * s + a1 * u0z + a2 * cz;
-  const double vp = vpar + apar * s;
+  const R bx = (R)F.bh[0], by = (R)F.bh[1], bz = (R)F.bh[2];
+  const R Bx = (R)F.Bv[0], By = (R)F.Bv[1], Bz = (R)F.Bv[2];
+  const R wds = (R)F.wd_scale;
+  const R vpar = dot3<R>(e.vx, e.vy, e.vz, bx, by, bz);
+  const R apar = dot3<R>(ax, ay, az, bx, by, bz);
+  const R wx = wds * (Ey * Bz - Ez * By);
+  const R wy = wds * (Ez * Bx - Ex * Bz);
+  const R wz = wds * (Ex * By - Ey * Bx);
+  const R u0x = (e.vx - vpar * bx) - wx;
+  const R u0y = (e.vy - vpar * by) - wy;
+  const R u0z = (e.vz - vpar * bz) - wz;
+  const R cx = by * u0z - bz * u0y;
+  const R cy = bz * u0x - bx * u0z;
+  const R cz = bx * u0y - by * u0x;
+  const R ph = (R)F.omega * s;
+  R sn, cs;
+  Mr::sincos_(ph, &sn, &cs);
+  const R sh = Mr::sin_(R(0.5) * ph);
+  const R omc = R(2) * sh * sh;
+  const R along = vpar * s + R(0.5) * apar * s * s;
+  const R io = (R)F.inv_omega;
+  const R a1 = sn * io, a2 = omc * io;
+  rx = e.x + (double)(along * bx + wx * s + a1 * u0x + a2 * cx);
+  ry = e.y + (double)(along * by + wy * s + a1 * u0y + a2 * cy);
+  rz = e.z + (double)(along * bz + wz * s + a1 * u0z + a2 * cz);
+  const R vp = vpar + apar * s;
   ux = vp * bx + wx + cs * u0x + sn * cx;
   uy = vp * by + wy + cs * u0y + sn * cy;
   uz = vp * bz + wz + cs * u0z + sn * cz;
 }
 
 // Smallest s >= 0 at which |v + a s|^2 reaches 2 k_a edge (energy at the band edge).
-AVM_FN double band_crossing(const RunParams& P, const Elec& e, double ax,
-                                                double ay, double az, double edge) {
-  const double C = dot3(e.vx, e.vy, e.vz, e.vx, e.vy, e.vz) - P.two_ka * edge;
-  if (C >= 0.0) return 0.0;
-  double r1 = 0.0, r2 = 0.0;
-  const int n = roots2(dot3(ax, ay, az, ax, ay, az), 2.0 * dot3(e.vx, e.vy, e.vz, ax, ay, az), C,
-                       r1, r2);
-  if (n >= 1 && r1 >= 0.0) return r1;
-  if (n == 2 && r2 >= 0.0) return r2;
-  return 0.0;
+template <class R>
+AVM_FN R band_crossing(const RunParams& P, const Elec<R>& e, R ax, R ay, R az, R edge) {
+  const R C = dot3<R>(e.vx, e.vy, e.vz, e.vx, e.vy, e.vz) - Sel<R>::two_ka(P) * edge;
+  if (C >= R(0)) return R(0);
+  R r1 = R(0), r2 = R(0);
+  const int n = roots2<R>(dot3<R>(ax, ay, az, ax, ay, az), R(2) * dot3<R>(e.vx, e.vy, e.vz, ax, ay, az),
+                          C, r1, r2);
+  if (n >= 1 && r1 >= R(0)) return r1;
+  if (n == 2 && r2 >= R(0)) return r2;
+  return R(0);
+}
+
+// New velocity after a real collision: the old direction turned by
+// (cos_t, phi = 2 pi uB), speed from the new energy; flight index advanced.
+template <class R>
+AVM_FN void scatter_to(Elec<R>& e, const RunParams& P, R cos_t, R uB, R e_new) {
+  const R v2 = dot3<R>(e.vx, e.vy, e.vz, e.vx, e.vy, e.vz);
+  R dx = R(0), dy = R(0), dz = R(1);
+  if (v2 > R(0)) {
+    const R inv = M<R>::rsqrt_(v2);
+    dx = e.vx * inv;
+    dy = e.vy * inv;
+    dz = e.vz * inv;
+  }
+  R ox, oy, oz;
+  turn<R>(dx, dy, dz, cos_t, uB, ox, oy, oz);
+  const R sp1 = M<R>::sqrt_(Sel<R>::two_ka(P) * e_new);
+  e.vx = sp1 * ox;
+  e.vy = sp1 * oy;
+  e.vz = sp1 * oz;
+  e.k += 1;
+}
+
+// Collision decision at energy en with selection value r_sel: -1 null,
+// -2 masked null (the chosen channel's window excludes en), otherwise the
+// channel: the smallest c with r_sel < interpolated cumulative rate c
+// (channel 0 first -- the elastic channel dominates -- then a binary search
+// over the rest; interpolated cumulative rates are non-decreasing in c).
+// `margin` returns the smallest relative distance of r_sel to a rate it was
+// compared with, or of en to the window edge it was compared with; `over`
+// tells whether en lies above the table.
+template <class R>
+AVM_FN int decide(const GasDev& G, const TabView<R>& T, R en, R r_sel, R& margin, bool& over) {
+  using Mr = M<R>;
+  const R x = en * Sel<R>::scale(G);
+  int32_t kb;
+  R f;
+  over = !(x < (R)G.n_bins);
+  if (over) {
+    kb = G.n_bins;
+    f = R(0);
+  } else {
+    const R fl = Mr::floor_(x);
+    kb = (int32_t)fl;
+    f = x - fl;
+  }
+  const R g1 = R(1) - f;
+  const bool in_lo = kb + 1 < T.n_lo;  // both nodes in the fast copy
+  const R* tot = Sel<R>::total(G);
+  const R* cz = Sel<R>::cum0(G);
+  R nu_tot, c0;
+  if (in_lo) {
+    nu_tot = lerp<R>(T.tot[kb], T.tot[kb + 1], g1, f);
+    c0 = lerp<R>(T.cum0[kb], T.cum0[kb + 1], g1, f);
+  } else {
+    nu_tot = over ? tot[kb] : lerp<R>(tot[kb], tot[kb + 1], g1, f);
+    c0 = over ? cz[kb] : lerp<R>(cz[kb], cz[kb + 1], g1, f);
+  }
+  R mg = Mr::abs_(r_sel - nu_tot);
+  if (r_sel >= nu_tot) {
+    margin = mg / r_sel;
+    return -1;
+  }
+  int c = 0;
+  R dm = Mr::abs_(r_sel - c0);
+  mg = dm < mg ? dm : mg;
+  if (!(r_sel < c0)) {
+    const int nc = G.n_ch;
+    const R* row0 = Sel<R>::cum(G) + (size_t)kb * nc;
+    const R* row1 = over ? row0 : row0 + nc;
+    int lo = 1, hi = nc - 1;  // answer in [lo, hi]
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      const R cm = over ? row0[mid] : lerp<R>(row0[mid], row1[mid], g1, f);
+      dm = Mr::abs_(r_sel - cm);
+      mg = dm < mg ? dm : mg;
+      if (r_sel < cm)
+        hi = mid;
+      else
+        lo = mid + 1;
+    }
+    c = lo;
+  }
+  margin = mg / r_sel;
+  const double e_lo = c == 0 ? G.ch0.e_lo : G.ch[c].e_lo;
+  const double e_hi = c == 0 ? G.ch0.e_hi : G.ch[c].e_hi;
+  const double ed = (double)en;
+  if (sizeof(R) == 4) {
+    const double dl = fabs(ed - e_lo), dh = fabs(ed - e_hi);
+    const double d = (dl < dh ? dl : dh) / (ed > 1e-30 ? ed : 1e-30);
+    margin = (R)d < margin ? (R)d : margin;
+  }
+  if (ed < e_lo || ed >= e_hi) return -2;
+  return c;
 }
 
 // One pass of the loop for electron `e`.  Returns STEP_DONE with `status`
-// set when the electron terminates, STEP_IONISED with `child` filled when an
-// ionisation spawned a secondary (the electron itself continues), otherwise
+// set when the electron terminates, STEP_IONISED (with the channel and
+// energy in `child`) when the collision is an ionisation -- the caller then
+// finishes it with complete_ionisation() before the next pass -- otherwise
 // STEP_CONTINUE.
-template <bool kBanded, int kField>
-AVM_FN int32_t flight_step(Elec& e, const GasDev& G, const FieldDev& F,
-                                               const RunParams& P, Child& child,
-                                               uint32_t& status) {
+template <class R, bool kBanded, int kField>
+AVM_FN int32_t flight_step(Elec<R>& e, const GasDev& G, const TabView<R>& T, const FieldDev& F,
+                           const RunParams& P, Child<R>& child, uint32_t& status) {
+  using Mr = M<R>;
+  constexpr bool kMixed = sizeof(R) == 4;
   // position valid?
-  status = region_status(F, e);
+  status = region_status<R>(F, e);
   if (status) return STEP_DONE;
   if (e.k >= P.k_max) {
     status = ST_ABANDONED;
@@ -393,24 +626,25 @@ AVM_FN int32_t flight_step(Elec& e, const GasDev& G, const FieldDev& F,
     return STEP_DONE;
   }
   const Block w = draw(P, e.aval, e.eid, e.k, 0);
-  const double u1 = u53(w.w0, w.w1);
-  const double u2 = u53(w.w2, w.w3);
-  double Ex = e.Ex, Ey = e.Ey, Ez = e.Ez;
+  const R u1 = Mr::uni(w.w0, w.w1);
+  const R u2 = Mr::uni(w.w2, w.w3);
+  R Ex = e.Ex, Ey = e.Ey, Ez = e.Ez;
   if (kField == FIELD_POLAR) {
-    polar_field(F, e.x, e.y, Ex, Ey);
-    Ez = 0.0;
+    polar_field<R>(F, e.x, e.y, Ex, Ey);
+    Ez = R(0);
   }
-  const double ax = -P.k_a * Ex, ay = -P.k_a * Ey, az = -P.k_a * Ez;
-  const double gam = kBanded ? G.band_gamma[e.band] : G.gamma;
-  const double inv_gam = kBanded ? G.band_inv[e.band] : G.inv_gamma;
-  const double tau = -log(u1) * inv_gam;
-  double tau_end = tau;
+  const R ka = Sel<R>::k_a(P);
+  const R ax = -ka * Ex, ay = -ka * Ey, az = -ka * Ez;
+  const R gam = kBanded ? T.bgam[e.band] : Sel<R>::gamma(G);
+  const R inv_gam = kBanded ? T.binv[e.band] : Sel<R>::inv_gamma(G);
+  const R tau = -Mr::log_(u1) * inv_gam;
+  R tau_end = tau;
   int cut = 0;  // 1: band edge, 2: time limit
   if (kBanded && e.band < G.n_bands - 1) {
-    const double fx = e.vx + ax * tau, fy = e.vy + ay * tau, fz = e.vz + az * tau;
-    const double edge = G.band_edge[e.band];
-    if (dot3(fx, fy, fz, fx, fy, fz) * P.inv_2ka >= edge) {
-      const double tc = band_crossing(P, e, ax, ay, az, edge);
+    const R fx = Mr::fma(ax, tau, e.vx), fy = Mr::fma(ay, tau, e.vy), fz = Mr::fma(az, tau, e.vz);
+    const R edge = T.bedge[e.band];
+    if (dot3<R>(fx, fy, fz, fx, fy, fz) * Sel<R>::inv_2ka(P) >= edge) {
+      const R tc = band_crossing<R>(P, e, ax, ay, az, edge);
       if (tc < tau_end) {
         tau_end = tc;
         cut = 1;
@@ -418,29 +652,31 @@ AVM_FN int32_t flight_step(Elec& e, const GasDev& G, const FieldDev& F,
     }
   }
   const double t_left = P.t_max - e.t;
-  if (t_left < tau_end) {
-    tau_end = t_left;
+  if (t_left < (double)tau_end) {
+    tau_end = (R)t_left;
     cut = 2;
   }
   // boundary first passage within (0, tau_end]
-  double rx, ry, rz, ux, uy, uz;
-  double s_exit = tau_end;
+  double rx, ry, rz;
+  R ux, uy, uz;
+  double s_exit = (double)tau_end;
   uint32_t side = 0;
   if (kField == FIELD_SLAB) {
-    side = slab_exit(e.z, e.vz, az, F.z_lo, F.z_hi, tau_end, s_exit);
-    propagate(F, P, e, ax, ay, az, Ex, Ey, Ez, side ? s_exit : tau_end, rx, ry, rz, ux, uy, uz);
+    side = slab_exit(e.z, (double)e.vz, (double)az, F.z_lo, F.z_hi, (double)tau_end, s_exit);
+    propagate<R>(F, e, ax, ay, az, Ex, Ey, Ez, side ? (R)s_exit : tau_end, rx, ry, rz, ux, uy, uz);
     if (side) rz = side == ST_HIGH ? F.z_hi : F.z_lo;
   } else {
-    propagate(F, P, e, ax, ay, az, Ex, Ey, Ez, tau_end, rx, ry, rz, ux, uy, uz);
+    propagate<R>(F, e, ax, ay, az, Ex, Ey, Ez, tau_end, rx, ry, rz, ux, uy, uz);
     const double r2 = rx * rx + ry * ry;
     if (r2 <= F.a2 || r2 >= F.b2) {
       // bisection on the inside/outside predicate (excursions that leave
       // and re-enter within one flight are not detected)
-      double lo = 0.0, hi = tau_end;
+      double lo = 0.0, hi = (double)tau_end;
       for (int it = 0; it < 60; ++it) {
         const double mid = 0.5 * (lo + hi);
-        double mx, my, mz, wx_, wy_, wz_;
-        propagate(F, P, e, ax, ay, az, Ex, Ey, Ez, mid, mx, my, mz, wx_, wy_, wz_);
+        double mx, my, mz;
+        R wx_, wy_, wz_;
+        propagate<R>(F, e, ax, ay, az, Ex, Ey, Ez, (R)mid, mx, my, mz, wx_, wy_, wz_);
         const double m2 = mx * mx + my * my;
         if (m2 <= F.a2 || m2 >= F.b2)
           hi = mid;
@@ -448,7 +684,7 @@ AVM_FN int32_t flight_step(Elec& e, const GasDev& G, const FieldDev& F,
           lo = mid;
       }
       s_exit = hi;
-      propagate(F, P, e, ax, ay, az, Ex, Ey, Ez, s_exit, rx, ry, rz, ux, uy, uz);
+      propagate<R>(F, e, ax, ay, az, Ex, Ey, Ez, (R)s_exit, rx, ry, rz, ux, uy, uz);
       const double q2 = rx * rx + ry * ry;
       side = q2 <= F.a2 ? ST_WIRE : ST_TUBE;
       const double sc = (side == ST_WIRE ? F.a : F.b) / sqrt(q2);
@@ -463,7 +699,7 @@ AVM_FN int32_t flight_step(Elec& e, const GasDev& G, const FieldDev& F,
     status = side;
     return STEP_DONE;
   }
-  e.t = e.t + tau_end;
+  e.t = e.t + (double)tau_end;
   if (cut == 2) {
     status = ST_TIME;
     return STEP_DONE;
@@ -477,120 +713,96 @@ AVM_FN int32_t flight_step(Elec& e, const GasDev& G, const FieldDev& F,
     return STEP_CONTINUE;
   }
   // collision?
-  const double en = dot3(e.vx, e.vy, e.vz, e.vx, e.vy, e.vz) * P.inv_2ka;
-  if (!(en < __builtin_inf())) {
+  const R en = dot3<R>(e.vx, e.vy, e.vz, e.vx, e.vy, e.vz) * Sel<R>::inv_2ka(P);
+  if (!(en < Mr::inf())) {
     status = ST_ERROR;
     return STEP_DONE;
   }
-  const double x = en * G.scale;
-  int32_t kb;
-  double f;
-  const bool over = !(x < (double)G.n_bins);
-  if (over) {
-    kb = G.n_bins;
-    f = 0.0;
-    e.n_over += 1;
-  } else {
-    const double fl = floor(x);
-    kb = (int32_t)fl;
-    f = x - fl;
+  R margin;
+  bool over;
+  int c = decide<R>(G, T, en, u2 * gam, margin, over);
+  if (kMixed && margin <= R(3.814697265625e-6)) {
+    // too close to call in FP32: decide again in FP64 for this state
+    const double vx = (double)e.vx, vy = (double)e.vy, vz = (double)e.vz;
+    const double en64 = dot3<double>(vx, vy, vz, vx, vy, vz) * P.inv_2ka;
+    double m64;
+    c = decide<double>(G, global_view<double>(G), en64, u53(w.w2, w.w3) * (double)gam, m64, over);
   }
-  const double g1 = 1.0 - f;
-  const double nu_tot = over ? G.total[kb] : g1 * G.total[kb] + f * G.total[kb + 1];
-  const double r_sel = u2 * gam;
-  if (r_sel >= nu_tot) {
-    e.n_null += 1;
+  if (over) e.n_over += 1;
+  if (c < 0) {
+    if (c == -1)
+      e.n_null += 1;
+    else
+      e.n_masked += 1;
     e.k += 1;
-    if (kBanded) e.band = band_of(G, en);
-    return STEP_CONTINUE;
-  }
-  // channel: the smallest c with r_sel < interpolated cumulative rate c.
-  // Channel 0 first (the elastic channel dominates), then a binary search
-  // over the rest; the interpolated cumulative rates are non-decreasing in c.
-  const int nc = G.n_ch;
-  const double* row0 = G.cum + (size_t)kb * nc;
-  const double* row1 = over ? row0 : row0 + nc;
-  auto cum_at = [&](int c) -> double { return over ? row0[c] : g1 * row0[c] + f * row1[c]; };
-  int c = 0;
-  if (!(r_sel < cum_at(0))) {
-    int lo = 1, hi = nc - 1;  // answer in [lo, hi]
-    while (lo < hi) {
-      const int mid = (lo + hi) >> 1;
-      if (r_sel < cum_at(mid))
-        hi = mid;
-      else
-        lo = mid + 1;
-    }
-    c = lo;
-  }
-  const ChanDev& ch = G.ch[c];
-  if (en < ch.e_lo || en >= ch.e_hi) {
-    e.n_masked += 1;
-    e.k += 1;
-    if (kBanded) e.band = band_of(G, en);
+    if (kBanded) e.band = band_of<R>(G, T, en);
     return STEP_CONTINUE;
   }
   e.n_real += 1;
-  if (ch.kind == CH_ATTACHMENT) {
+  const int32_t kind = c == 0 ? G.ch0.kind : G.ch[c].kind;
+  if (kind == CH_ATTACHMENT) {
     status = ST_ATTACHED;
     return STEP_DONE;
   }
-  // direction before the collision
-  const double sp0 = sqrt(dot3(e.vx, e.vy, e.vz, e.vx, e.vy, e.vz));
-  double dx = 0.0, dy = 0.0, dz = 1.0;
-  if (sp0 > 0.0) {
-    const double inv = 1.0 / sp0;
-    dx = e.vx * inv;
-    dy = e.vy * inv;
-    dz = e.vz * inv;
+  if (kind == CH_IONISATION) {
+    // finished by complete_ionisation() (the caller batches it)
+    child.pen = en;
+    child.pc = c;
+    return STEP_IONISED;
   }
   const Block w1 = draw(P, e.aval, e.eid, e.k, 1);
-  const double uA = u53(w1.w0, w1.w1);
-  const double uB = u53(w1.w2, w1.w3);
-  const double phi = 6.283185307179586 * uB;
-  double e_new, cos_t;
-  int32_t ret = STEP_CONTINUE;
-  if (ch.kind == CH_ELASTIC) {
-    const double cchi = ch.angular ? 1.0 - 2.0 * uA / (1.0 + (1.0 - uA) * (en * ch.inv_screen8))
-                                   : 1.0 - 2.0 * uA;
-    e_new = en * (1.0 - ch.el_loss * (1.0 - cchi));
-    cos_t = (ch.mu + cchi) / sqrt(ch.mu2p1 + ch.two_mu * cchi);
-  } else if (ch.kind == CH_EXCITATION) {
+  const R uA = Mr::uni(w1.w0, w1.w1);
+  const R uB = Mr::uni(w1.w2, w1.w3);
+  const ChanP<R>& ch = c == 0 ? Sel<R>::ch0(G) : Sel<R>::ch(G)[c];
+  R e_new, cos_t;
+  if (kind == CH_ELASTIC) {
+    const R cchi = ch.angular ? R(1) - R(2) * uA / Mr::fma(R(1) - uA, en * ch.inv_screen8, R(1))
+                              : R(1) - R(2) * uA;
+    e_new = en * (R(1) - ch.el_loss * (R(1) - cchi));
+    cos_t = (ch.mu + cchi) * Mr::rsqrt_(Mr::fma(ch.two_mu, cchi, ch.mu2p1));
+  } else {  // excitation
     e_new = en - ch.loss;
-    cos_t = 1.0 - 2.0 * uA;
-  } else {
-    const double avail = en - ch.loss;
-    const Block w2 = draw(P, e.aval, e.eid, e.k, 2);
-    const Block w3 = draw(P, e.aval, e.eid, e.k, 3);
-    const double uS = u53(w2.w0, w2.w1);
-    const double uC = u53(w2.w2, w2.w3);
-    const double uP = u53(w3.w0, w3.w1);
-    const double es = ch.split ? ch.split_w * tan(uS * atan(avail * ch.atan_scale)) : uS * avail;
-    e_new = avail - es;
-    cos_t = 1.0 - 2.0 * uA;
-    const double ct = 1.0 - 2.0 * uC;
-    const double st2 = 1.0 - ct * ct;
-    const double stt = st2 > 0.0 ? sqrt(st2) : 0.0;
-    double sp, cp;
-    sincos(6.283185307179586 * uP, &sp, &cp);
-    const double vs = sqrt(P.two_ka * es);
-    child.vx = vs * (stt * cp);
-    child.vy = vs * (stt * sp);
-    child.vz = vs * ct;
-    child.e = es;
-    child.eid = (((uint64_t)w3.w3 << 32) | (uint64_t)w3.w2) & 0x7FFFFFFFFFFFFFFFull;
-    e.n_ion += 1;
-    ret = STEP_IONISED;
+    cos_t = R(1) - R(2) * uA;
   }
-  double ox, oy, oz;
-  turn(dx, dy, dz, cos_t, phi, ox, oy, oz);
-  const double sp1 = sqrt(P.two_ka * e_new);
-  e.vx = sp1 * ox;
-  e.vy = sp1 * oy;
-  e.vz = sp1 * oz;
-  e.k += 1;
-  if (kBanded) e.band = band_of(G, e_new);
-  return ret;
+  scatter_to<R>(e, P, cos_t, uB, e_new);
+  if (kBanded) e.band = band_of<R>(G, T, e_new);
+  return STEP_CONTINUE;
+}
+
+// Finishes an ionisation decided by flight_step (blocks j = 1..3 of the
+// electron's flight k): energy split, the primary's new direction, the
+// secondary's energy, direction and id.
+template <class R, bool kBanded>
+AVM_FN void complete_ionisation(Elec<R>& e, const GasDev& G, const TabView<R>& T,
+                                const RunParams& P, Child<R>& child) {
+  using Mr = M<R>;
+  const int c = child.pc;
+  const ChanP<R>& ch = c == 0 ? Sel<R>::ch0(G) : Sel<R>::ch(G)[c];
+  const R avail = child.pen - ch.loss;
+  const Block w1 = draw(P, e.aval, e.eid, e.k, 1);
+  const Block w2 = draw(P, e.aval, e.eid, e.k, 2);
+  const Block w3 = draw(P, e.aval, e.eid, e.k, 3);
+  const R uA = Mr::uni(w1.w0, w1.w1);
+  const R uB = Mr::uni(w1.w2, w1.w3);
+  const R uS = Mr::uni(w2.w0, w2.w1);
+  const R uC = Mr::uni(w2.w2, w2.w3);
+  const R uP = Mr::uni(w3.w0, w3.w1);
+  const R es = ch.split ? ch.split_w * Mr::tan_(uS * Mr::atan_(avail * ch.atan_scale)) : uS * avail;
+  const R e_new = avail - es;
+  const R ct = R(1) - R(2) * uC;
+  const R st2 = Mr::fma(-ct, ct, R(1));
+  const R stt = st2 > R(0) ? Mr::sqrt_(st2) : R(0);
+  R sp, cp;
+  Mr::sincospi_(R(2) * uP, &sp, &cp);
+  const R vs = Mr::sqrt_(Sel<R>::two_ka(P) * es);
+  child.vx = vs * (stt * cp);
+  child.vy = vs * (stt * sp);
+  child.vz = vs * ct;
+  child.e = es;
+  child.eid = (((uint64_t)w3.w3 << 32) | (uint64_t)w3.w2) & 0x7FFFFFFFFFFFFFFFull;
+  e.n_ion += 1;
+  scatter_to<R>(e, P, R(1) - R(2) * uA, uB, e_new);
+  if (kBanded) e.band = band_of<R>(G, T, e_new);
 }
 
 }  // namespace avm

@@ -18,7 +18,8 @@ struct Store {
   double *x0, *y0, *z0, *t0, *vx0, *vy0, *vz0, *e0;
   uint64_t *eid, *parent;
   uint32_t* aval;
-  uint32_t* ready;  // batched: slot published when ready[s] == epoch
+  uint32_t* qready;  // batched: queue entry q published when qready[q] == epoch
+  uint32_t* qslot;   // batched: slot of queue entry q
   double *x1, *y1, *z1, *t1, *e1, *vx1, *vy1, *vz1;
   uint32_t *k1, *band1;
   uint32_t *status, *n_real, *n_ion, *n_null, *n_masked, *n_band, *n_over;
@@ -28,12 +29,13 @@ struct Store {
 // Device counters of a run.
 struct Counters {
   unsigned long long tail;     // slots requested (electrons created, incl. dropped)
-  unsigned long long head;     // batched: slots claimed by lanes
+  unsigned long long qhead;    // batched: queue entries claimed by lanes
   unsigned long long live;     // batched: electrons created and not yet terminated
   unsigned long long next;     // plain: size of the next active list
   unsigned long long err;      // bad primary avalanche id
   unsigned long long timeout;  // a transport kernel ran out of its time budget
-  unsigned long long _pad[2];
+  unsigned long long qtail;    // batched: queue entries published or being published
+  unsigned long long epoch;    // run counter (bumped by every reset; tags queue entries)
 };
 
 // Per-avalanche statistics (and totals, with the status histogram).
@@ -58,18 +60,24 @@ hipError_t launch_build_rates(const double* sigma, const int32_t* values_kind, i
 hipError_t launch_build_bands(const double* binmax, int n_bins, int band_bins, int n_bands,
                               double e_max, double* band_gamma, double* band_inv, double* band_edge,
                               double* gamma_out, hipStream_t st);
-hipError_t launch_load_primaries(const PrimaryRec* prim, uint64_t n, const Store& S, uint32_t epoch,
-                                 double k_a, uint32_t n_aval, uint32_t* active, Counters* ctr,
-                                 int plain, hipStream_t st);
+hipError_t launch_load_primaries(const PrimaryRec* prim, uint64_t n, const Store& S, double k_a,
+                                 uint32_t n_aval, uint32_t* active, Counters* ctr, int plain,
+                                 hipStream_t st);
 hipError_t launch_reset(Counters* ctr, uint64_t n_prim, AvalStats* stats, uint32_t n_aval,
                         Totals* tot, hipStream_t st);
-hipError_t launch_generation(int banded, int field_kind, const GasDev& G, const FieldDev& F,
-                             const RunParams& P, const Store& S, const uint32_t* active,
-                             uint32_t n_active, uint32_t* next, Counters* ctr, hipStream_t st);
-hipError_t launch_persistent(int banded, int field_kind, const GasDev& G, const FieldDev& F,
-                             const RunParams& P, const Store& S, Counters* ctr, uint32_t epoch,
+hipError_t launch_generation(int fp32, int banded, int field_kind, const GasDev& G,
+                             const FieldDev& F, const RunParams& P, const Store& S,
+                             const uint32_t* active, uint32_t n_active, uint32_t* next,
+                             Counters* ctr, hipStream_t st);
+hipError_t launch_persistent(int fp32, int banded, int field_kind, const GasDev& G,
+                             const FieldDev& F, const RunParams& P, const Store& S, Counters* ctr,
                              int flights_per_pass, int grid, int block, hipStream_t st);
-hipError_t persistent_occupancy(int banded, int field_kind, int block, int* blocks_per_cu);
+hipError_t persistent_occupancy(int fp32, int banded, int field_kind, int block,
+                                int* blocks_per_cu);
+hipError_t launch_tables_f32(const double* cum, const double* total, const double* cum0,
+                             size_t n_cum, int n_nodes, const double* bg, const double* be,
+                             int n_bands, float* cum_f, float* total_f, float* cum0_f, float* bg_f,
+                             float* bi_f, float* be_f, hipStream_t st);
 hipError_t launch_stats(const Store& S, const Counters* ctr, AvalStats* stats, Totals* tot,
                         hipStream_t st);
 

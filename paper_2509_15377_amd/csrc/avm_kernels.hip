@@ -8,7 +8,10 @@ namespace avm {
 
 namespace {
 
-constexpr int kBlock = 256;
+constexpr int kBlock = 256;        // set-up, plain and statistics kernels
+constexpr int kPBlock = 512;       // persistent kernel: one block of 8 waves per CU
+constexpr int kLdsBytes = 32768;   // bytes of each table slice staged in LDS
+constexpr int kLdsBands = 1024;    // band tables staged in LDS up to this size
 
 // ---------------------------------------------------------------------------
 // wave-level helpers (wave64)
@@ -30,8 +33,9 @@ __device__ __forceinline__ unsigned long long wave_alloc(unsigned long long* ctr
   return base + prefix;
 }
 
-__device__ __forceinline__ double energy(const RunParams& P, double vx, double vy, double vz) {
-  return dot3(vx, vy, vz, vx, vy, vz) * P.inv_2ka;
+template <class R>
+AVM_FN R energy(const RunParams& P, R vx, R vy, R vz) {
+  return dot3<R>(vx, vy, vz, vx, vy, vz) * Sel<R>::inv_2ka(P);
 }
 
 // ---------------------------------------------------------------------------
@@ -119,11 +123,15 @@ __global__ void k_reset(Counters* ctr, uint64_t n_prim, AvalStats* stats, uint32
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i == 0) {
     ctr->tail = n_prim;
-    ctr->head = 0;
+    ctr->qhead = 0;
+    ctr->qtail = n_prim;
     ctr->live = n_prim;
     ctr->next = 0;
     ctr->err = 0;
     ctr->timeout = 0;
+    // a new run tag: queue entries of earlier runs no longer count as ready
+    unsigned long long ep = (ctr->epoch + 1ull) & 0xFFFFFFFFull;
+    ctr->epoch = ep == 0 ? 1ull : ep;
     for (int j = 0; j < 8; ++j) tot->c[j] = 0;
     for (int j = 0; j < 9; ++j) tot->status[j] = 0;
   }
@@ -132,10 +140,11 @@ __global__ void k_reset(Counters* ctr, uint64_t n_prim, AvalStats* stats, uint32
 
 // Primaries -> slots [0, n): start record, zeroed end record, published.
 __global__ void k_load_primaries(const PrimaryRec* __restrict__ prim, uint64_t n, Store S,
-                                 uint32_t epoch, double k_a, uint32_t n_aval, uint32_t* active,
-                                 Counters* ctr, int plain) {
+                                 double k_a, uint32_t n_aval, uint32_t* active, Counters* ctr,
+                                 int plain) {
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  const uint32_t epoch = (uint32_t)ctr->epoch;
   const PrimaryRec p = prim[i];
   uint32_t a = p.aval;
   if (a >= n_aval) {
@@ -168,48 +177,48 @@ __global__ void k_load_primaries(const PrimaryRec* __restrict__ prim, uint64_t n
     S.n_band[i] = 0; S.n_over[i] = 0; S.status[i] = 0;
     active[i] = (uint32_t)i;
   }
-  S.ready[i] = epoch;
+  S.qslot[i] = (uint32_t)i;
+  S.qready[i] = epoch;
 }
 
-__device__ __forceinline__ void slab_field(const FieldDev& F, uint32_t aval, Elec& e) {
+template <class R>
+AVM_FN void slab_field(const FieldDev& F, uint32_t aval, Elec<R>& e) {
   const double* E = F.E + 3 * (size_t)(F.n_E == 1 ? 0u : aval);
-  e.Ex = E[0];
-  e.Ey = E[1];
-  e.Ez = E[2];
+  e.Ex = (R)E[0];
+  e.Ey = (R)E[1];
+  e.Ez = (R)E[2];
 }
 
-__device__ __forceinline__ void write_end(const Store& S, uint32_t s, const Elec& e,
-                                          const RunParams& P, uint32_t status) {
+template <class R>
+AVM_FN void write_end(const Store& S, uint32_t s, const Elec<R>& e, const RunParams& P,
+                      uint32_t status) {
   S.x1[s] = e.x; S.y1[s] = e.y; S.z1[s] = e.z; S.t1[s] = e.t;
-  S.e1[s] = energy(P, e.vx, e.vy, e.vz);
+  S.e1[s] = (double)energy<R>(P, e.vx, e.vy, e.vz);
   S.status[s] = status;
   S.n_real[s] = e.n_real; S.n_ion[s] = e.n_ion; S.n_null[s] = e.n_null;
   S.n_masked[s] = e.n_masked; S.n_band[s] = e.n_band; S.n_over[s] = e.n_over;
 }
 
-__device__ __forceinline__ void write_start(const Store& S, uint64_t s, const Elec& parent,
-                                            const Child& c) {
+template <class R>
+AVM_FN void write_start(const Store& S, uint64_t s, const Elec<R>& parent, const Child<R>& c) {
   S.x0[s] = parent.x; S.y0[s] = parent.y; S.z0[s] = parent.z; S.t0[s] = parent.t;
-  S.vx0[s] = c.vx; S.vy0[s] = c.vy; S.vz0[s] = c.vz;
-  S.e0[s] = c.e;
+  S.vx0[s] = (double)c.vx; S.vy0[s] = (double)c.vy; S.vz0[s] = (double)c.vz;
+  S.e0[s] = (double)c.e;
   S.eid[s] = c.eid;
   S.parent[s] = parent.eid;
   S.aval[s] = parent.aval;
 }
 
-// A fresh electron from its start record.
-template <bool kBanded, int kField>
-__device__ __forceinline__ void load_fresh(const Store& S, const GasDev& G, const FieldDev& F,
-                                           const RunParams& P, uint64_t s, Elec& e) {
-  e.x = S.x0[s]; e.y = S.y0[s]; e.z = S.z0[s]; e.t = S.t0[s];
-  e.vx = S.vx0[s]; e.vy = S.vy0[s]; e.vz = S.vz0[s];
-  e.eid = S.eid[s];
-  e.aval = S.aval[s];
+// Counters, band and (slab) field of an electron whose position, velocity,
+// id and avalanche are set.
+template <class R, bool kBanded, int kField>
+AVM_FN void load_elec_tail(const GasDev& G, const TabView<R>& T, const FieldDev& F,
+                           const RunParams& P, Elec<R>& e) {
   e.k = 0;
   e.n_real = 0; e.n_ion = 0; e.n_null = 0; e.n_masked = 0; e.n_band = 0; e.n_over = 0;
-  e.band = kBanded ? band_of(G, energy(P, e.vx, e.vy, e.vz)) : G.n_bands - 1;
-  e.Ex = 0.0; e.Ey = 0.0; e.Ez = 0.0;
-  if (kField == FIELD_SLAB) slab_field(F, e.aval, e);
+  e.band = kBanded ? band_of<R>(G, T, energy<R>(P, e.vx, e.vy, e.vz)) : G.n_bands - 1;
+  e.Ex = R(0); e.Ey = R(0); e.Ez = R(0);
+  if (kField == FIELD_SLAB) slab_field<R>(F, e.aval, e);
 }
 
 // ---------------------------------------------------------------------------
@@ -219,36 +228,37 @@ __device__ __forceinline__ void load_fresh(const Store& S, const GasDev& G, cons
 // survivors and the new secondaries form the next active list (the paper's
 // stack processing: inactive removed, new added), appended with one atomic
 // per wave.
-template <bool kBanded, int kField>
+template <class R, bool kBanded, int kField>
 __global__ void __launch_bounds__(kBlock) k_generation(GasDev G, FieldDev F, RunParams P, Store S,
                                                        const uint32_t* __restrict__ active,
                                                        uint32_t n_active, uint32_t* __restrict__ next,
                                                        Counters* ctr) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   const bool mine = i < n_active;
+  const TabView<R> T = global_view<R>(G);
   bool ionised = false;
   uint32_t slot = 0;
-  Elec e;
-  Child child;
+  Elec<R> e;
+  Child<R> child;
   if (mine) {
     slot = active[i];
     e.x = S.x1[slot]; e.y = S.y1[slot]; e.z = S.z1[slot]; e.t = S.t1[slot];
-    e.vx = S.vx1[slot]; e.vy = S.vy1[slot]; e.vz = S.vz1[slot];
+    e.vx = (R)S.vx1[slot]; e.vy = (R)S.vy1[slot]; e.vz = (R)S.vz1[slot];
     e.eid = S.eid[slot];
     e.aval = S.aval[slot];
     e.k = S.k1[slot];
-    e.band = kBanded ? (e.k == 0 ? band_of(G, energy(P, e.vx, e.vy, e.vz)) : (int32_t)S.band1[slot])
+    e.band = kBanded ? (e.k == 0 ? band_of<R>(G, T, energy<R>(P, e.vx, e.vy, e.vz)) : (int32_t)S.band1[slot])
                      : G.n_bands - 1;
     e.n_real = S.n_real[slot]; e.n_ion = S.n_ion[slot]; e.n_null = S.n_null[slot];
     e.n_masked = S.n_masked[slot]; e.n_band = S.n_band[slot]; e.n_over = S.n_over[slot];
-    e.Ex = 0.0; e.Ey = 0.0; e.Ez = 0.0;
-    if (kField == FIELD_SLAB) slab_field(F, e.aval, e);
+    e.Ex = R(0); e.Ey = R(0); e.Ez = R(0);
+    if (kField == FIELD_SLAB) slab_field<R>(F, e.aval, e);
     uint32_t status = 0;
     int32_t r;
     const uint64_t t_start = wall_clock64();
     uint32_t n = 0;
     do {
-      r = flight_step<kBanded, kField>(e, G, F, P, child, status);
+      r = flight_step<R, kBanded, kField>(e, G, T, F, P, child, status);
       if (r == STEP_CONTINUE && (++n & 4095u) == 0 && wall_clock64() - t_start > P.budget_ticks) {
         // out of time: stop this electron, flag the run
         __hip_atomic_store(&ctr->timeout, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -259,9 +269,10 @@ __global__ void __launch_bounds__(kBlock) k_generation(GasDev G, FieldDev F, Run
     if (r == STEP_DONE) {
       write_end(S, slot, e, P, status);
     } else {
+      complete_ionisation<R, kBanded>(e, G, T, P, child);
       ionised = true;
       S.x1[slot] = e.x; S.y1[slot] = e.y; S.z1[slot] = e.z; S.t1[slot] = e.t;
-      S.vx1[slot] = e.vx; S.vy1[slot] = e.vy; S.vz1[slot] = e.vz;
+      S.vx1[slot] = (double)e.vx; S.vy1[slot] = (double)e.vy; S.vz1[slot] = (double)e.vz;
       S.k1[slot] = e.k; S.band1[slot] = (uint32_t)e.band;
       S.n_real[slot] = e.n_real; S.n_ion[slot] = e.n_ion; S.n_null[slot] = e.n_null;
       S.n_masked[slot] = e.n_masked; S.n_band[slot] = e.n_band; S.n_over[slot] = e.n_over;
@@ -272,9 +283,9 @@ __global__ void __launch_bounds__(kBlock) k_generation(GasDev G, FieldDev F, Run
   const unsigned long long cs = wave_alloc(&ctr->tail, ionised);
   const bool stored = ionised && cs < S.capacity;
   if (stored) {
-    write_start(S, cs, e, child);
+    write_start<R>(S, cs, e, child);
     S.x1[cs] = e.x; S.y1[cs] = e.y; S.z1[cs] = e.z; S.t1[cs] = e.t;
-    S.vx1[cs] = child.vx; S.vy1[cs] = child.vy; S.vz1[cs] = child.vz;
+    S.vx1[cs] = (double)child.vx; S.vy1[cs] = (double)child.vy; S.vz1[cs] = (double)child.vz;
     S.k1[cs] = 0; S.band1[cs] = 0;
     S.n_real[cs] = 0; S.n_ion[cs] = 0; S.n_null[cs] = 0; S.n_masked[cs] = 0;
     S.n_band[cs] = 0; S.n_over[cs] = 0; S.status[cs] = 0;
@@ -288,22 +299,99 @@ __global__ void __launch_bounds__(kBlock) k_generation(GasDev G, FieldDev F, Run
 // ---------------------------------------------------------------------------
 // batched mode: persistent kernel fed by a device work queue
 // ---------------------------------------------------------------------------
-// The queue is the slot store itself: slots are handed out in order by
-// `tail` (creation) and claimed in order by `head`; slot s is published
-// by a release store of the run's epoch into ready[s] after its start record
-// is written, and read after an acquire load observes it.  `live` counts
-// electrons created and not yet terminated: it is raised before a slot is
-// published and lowered after an end record is written, so live == 0 means
-// no electron exists and none can appear -- every lane then leaves.
-template <bool kBanded, int kField>
-__global__ void __launch_bounds__(kBlock) k_persistent(GasDev G, FieldDev F, RunParams P, Store S,
-                                                       Counters* ctr, uint32_t epoch,
-                                                       int flights_per_pass) {
+// Device-coherent accesses (scope: agent, relaxed) for the data handed from
+// one wave to another: they are performed at the device's point of
+// coherence, so they need no L2 write-back or invalidation (which the
+// release/acquire forms would issue on every XCD-local L2).
+AVM_FN void st_coh(double* p, double v) {
+  __hip_atomic_store(reinterpret_cast<unsigned long long*>(p), __builtin_bit_cast(unsigned long long, v),
+                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+AVM_FN void st_coh(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+AVM_FN void st_coh(uint32_t* p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+AVM_FN double ld_coh(const double* p) {
+  return __builtin_bit_cast(double, __hip_atomic_load(reinterpret_cast<const unsigned long long*>(p),
+                                                      __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+template <class T>
+AVM_FN T ld_coh_int(const T* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// wait until every store this wave issued has been acknowledged
+AVM_FN void wait_stores() { __builtin_amdgcn_s_waitcnt(0x0F70); /* vmcnt(0) */ }
+
+// Child records handed from a lane to an idle lane of the same wave.
+struct Xfer {
+  double x[64], y[64], z[64], t[64], vx[64], vy[64], vz[64];
+  uint64_t eid[64];
+  uint32_t slot[64], aval[64];
+};
+
+// Occupancy target of the persistent kernel (waves per SIMD); the register
+// budget follows from it.
+#ifndef AVM_PERSISTENT_WAVES_PER_EU
+#define AVM_PERSISTENT_WAVES_PER_EU 2
+#endif
+
+// Every lane carries one electron at a time through up to `flights_per_pass`
+// flights; a lane stops early when its electron ends or ionises (the
+// secondary waits in registers).  At the end of a pass the wave, in
+// lockstep:
+//   1. allocates storage slots for its new secondaries (one atomic);
+//   2. hands secondaries to its own idle lanes through LDS (ballot/mbcnt
+//      ranks: the k-th secondary goes to the k-th idle lane);
+//   3. publishes the remaining secondaries on the global queue (one atomic
+//      on qtail; records written device-coherent, then the entry's ready
+//      word after the record stores are acknowledged);
+//   4. updates `live` (electrons in existence) once with its net change;
+//   5. lets its still-idle lanes claim queue entries (one atomic on qhead)
+//      and picks up entries whose ready word shows the run's epoch.
+// A lane leaves when it is idle with no usable claim and live == 0: then no
+// electron exists anywhere and none can appear.
+template <class R, bool kBanded, int kField>
+__global__ void __launch_bounds__(kPBlock)
+    __attribute__((amdgpu_waves_per_eu(AVM_PERSISTENT_WAVES_PER_EU, AVM_PERSISTENT_WAVES_PER_EU)))
+    k_persistent(GasDev G, FieldDev F, RunParams P, Store S, Counters* ctr, int flights_per_pass) {
+  const uint32_t epoch = (uint32_t)ctr->epoch;
   constexpr unsigned long long kNone = ~0ull;
-  bool has = false, done = false;
+  __shared__ Xfer xfer_all[kPBlock / 64];
+  // hot table slices: total rate and cumulative column 0 on the lowest
+  // nodes, and the band tables, one copy per block
+  constexpr int kLdsNodes = kLdsBytes / (int)sizeof(R);
+  __shared__ R s_tot[kLdsNodes], s_cum0[kLdsNodes];
+  __shared__ R s_bg[kLdsBands], s_bi[kLdsBands], s_be[kLdsBands];
+  const TabView<R> Tg = global_view<R>(G);
+  const int n_lo = G.n_bins + 1 < kLdsNodes ? G.n_bins + 1 : kLdsNodes;
+  for (int k = threadIdx.x; k < n_lo; k += kPBlock) {
+    s_tot[k] = Tg.tot[k];
+    s_cum0[k] = Tg.cum0[k];
+  }
+  const bool bands_lds = G.n_bands <= kLdsBands;
+  if (bands_lds)
+    for (int b = threadIdx.x; b < G.n_bands; b += kPBlock) {
+      s_bg[b] = Tg.bgam[b];
+      s_bi[b] = Tg.binv[b];
+      s_be[b] = Tg.bedge[b];
+    }
+  __syncthreads();
+  TabView<R> T{s_tot, s_cum0, n_lo, Tg.bgam, Tg.binv, Tg.bedge};
+  if (bands_lds) {
+    T.bgam = s_bg;
+    T.binv = s_bi;
+    T.bedge = s_be;
+  }
+  Xfer& X = xfer_all[threadIdx.x >> 6];
+  const uint32_t lane = __lane_id();
+  bool has = false, done = false, cp = false;
   unsigned long long claim = kNone;
   uint32_t slot = 0;
-  Elec e;
+  Elec<R> e;
+  Child<R> child;
+  double cx = 0.0, cy = 0.0, cz = 0.0, ct = 0.0;  // where the child was born
   const uint64_t t_start = wall_clock64();
   for (;;) {
     if (wall_clock64() - t_start > P.budget_ticks) {
@@ -311,42 +399,132 @@ __global__ void __launch_bounds__(kBlock) k_persistent(GasDev G, FieldDev F, Run
       __hip_atomic_store(&ctr->timeout, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       break;
     }
-    if (!has && !done) {
-      if (claim == kNone)
-        claim = __hip_atomic_fetch_add(&ctr->head, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (claim < S.capacity &&
-          __hip_atomic_load(&S.ready[claim], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == epoch) {
-        slot = (uint32_t)claim;
-        claim = kNone;
-        load_fresh<kBanded, kField>(S, G, F, P, slot, e);
-        has = true;
-      } else if (__hip_atomic_load(&ctr->live, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
-        done = true;
-      }
-    }
-    if (__ballot(!done) == 0) break;
-    if (__ballot(has) == 0) {
-      __builtin_amdgcn_s_sleep(4);
-      continue;
-    }
-    for (int f = 0; f < flights_per_pass && has; ++f) {
-      Child child;
+    // ---- transport pass
+    uint32_t ended = 0;
+    for (int f = 0; f < flights_per_pass && has && !cp; ++f) {
       uint32_t status = 0;
-      const int32_t r = flight_step<kBanded, kField>(e, G, F, P, child, status);
+      const int32_t r = flight_step<R, kBanded, kField>(e, G, T, F, P, child, status);
       if (r == STEP_IONISED) {
-        const unsigned long long cs =
-            __hip_atomic_fetch_add(&ctr->tail, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (cs < S.capacity) {
-          __hip_atomic_fetch_add(&ctr->live, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          write_start(S, cs, e, child);
-          __hip_atomic_store(&S.ready[cs], epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        }
+        cp = true;
       } else if (r == STEP_DONE) {
-        write_end(S, slot, e, P, status);
-        __hip_atomic_fetch_add(&ctr->live, ~0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        write_end<R>(S, slot, e, P, status);
         has = false;
+        ended = 1;
       }
     }
+    // ---- ionisations of this pass, finished together
+    if (cp) {
+      complete_ionisation<R, kBanded>(e, G, T, P, child);
+      cx = e.x; cy = e.y; cz = e.z; ct = e.t;
+    }
+    // ---- exchange (wave in lockstep from here)
+    // 1. storage slots for all secondaries of this pass (dropped beyond the
+    //    capacity; the stored ones are the lowest-ranked, slots are handed
+    //    out in lane order)
+    const unsigned long long cs = wave_alloc(&ctr->tail, cp);
+    const bool stored = cp && cs < S.capacity;
+    const uint64_t m_child = __ballot(stored);
+    const uint64_t m_idle = __ballot(!has && !done && claim == kNone);
+    const uint32_t n_child = __popcll(m_child), n_idle = __popcll(m_idle);
+    const uint32_t n_match = n_child < n_idle ? n_child : n_idle;
+    const uint32_t rank_c = __builtin_amdgcn_mbcnt_hi((uint32_t)(m_child >> 32),
+                                                      __builtin_amdgcn_mbcnt_lo((uint32_t)m_child, 0u));
+    const uint32_t rank_i = __builtin_amdgcn_mbcnt_hi((uint32_t)(m_idle >> 32),
+                                                      __builtin_amdgcn_mbcnt_lo((uint32_t)m_idle, 0u));
+    const bool local = stored && rank_c < n_match;
+    // 3. queue entries for the secondaries no idle lane of this wave takes
+    const unsigned long long q = wave_alloc(&ctr->qtail, stored && !local);
+    if (stored) {
+      // start record: the electron's output; queued ones are also read by
+      // other waves, so those go out device-coherent
+      if (local) {
+        S.x0[cs] = cx; S.y0[cs] = cy; S.z0[cs] = cz; S.t0[cs] = ct;
+        S.vx0[cs] = (double)child.vx; S.vy0[cs] = (double)child.vy; S.vz0[cs] = (double)child.vz;
+        S.eid[cs] = child.eid;
+        S.aval[cs] = e.aval;
+        X.x[rank_c] = cx; X.y[rank_c] = cy; X.z[rank_c] = cz; X.t[rank_c] = ct;
+        X.vx[rank_c] = (double)child.vx; X.vy[rank_c] = (double)child.vy;
+        X.vz[rank_c] = (double)child.vz;
+        X.eid[rank_c] = child.eid;
+        X.slot[rank_c] = (uint32_t)cs;
+        X.aval[rank_c] = e.aval;
+      } else {
+        st_coh(&S.x0[cs], cx); st_coh(&S.y0[cs], cy); st_coh(&S.z0[cs], cz); st_coh(&S.t0[cs], ct);
+        st_coh(&S.vx0[cs], (double)child.vx); st_coh(&S.vy0[cs], (double)child.vy);
+        st_coh(&S.vz0[cs], (double)child.vz);
+        st_coh(&S.eid[cs], child.eid);
+        st_coh(&S.aval[cs], e.aval);
+        st_coh(&S.qslot[q], (uint32_t)cs);
+      }
+      S.e0[cs] = (double)child.e;
+      S.parent[cs] = e.eid;
+    }
+    // publish queue entries once their records are acknowledged
+    wait_stores();
+    if (stored && !local) st_coh(&S.qready[q], epoch);
+    // 2. idle lanes of this wave take the local secondaries
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const bool take = (m_idle >> lane & 1) && rank_i < n_match;
+    if (take) {
+      e.x = X.x[rank_i]; e.y = X.y[rank_i]; e.z = X.z[rank_i]; e.t = X.t[rank_i];
+      e.vx = (R)X.vx[rank_i]; e.vy = (R)X.vy[rank_i]; e.vz = (R)X.vz[rank_i];
+      e.eid = X.eid[rank_i];
+      e.aval = X.aval[rank_i];
+      slot = X.slot[rank_i];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // 4. net change of the number of electrons in existence
+    {
+      const int delta = (int)n_child - (int)__popcll(__ballot(ended != 0));
+      if (delta != 0 && lane == (uint32_t)__builtin_ctzll(__ballot(1)))
+        __hip_atomic_fetch_add(&ctr->live, (unsigned long long)(long long)delta, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+    }
+    cp = false;
+    // 5. still-idle lanes claim queue entries while the queue has some
+    const bool want = !has && !done && claim == kNone && !take;
+    const uint64_t m_want = __ballot(want);
+    if (m_want) {
+      const unsigned long long qt = ld_coh_int(&ctr->qtail);
+      const unsigned long long qh = ld_coh_int(&ctr->qhead);
+      const unsigned long long avail = qt > qh ? qt - qh : 0ull;
+      const uint32_t n_want = __popcll(m_want);
+      const uint32_t n_take = avail < n_want ? (uint32_t)avail : n_want;
+      if (n_take) {
+        const uint32_t rk = __builtin_amdgcn_mbcnt_hi((uint32_t)(m_want >> 32),
+                                                      __builtin_amdgcn_mbcnt_lo((uint32_t)m_want, 0u));
+        unsigned long long base = 0;
+        if (want && rk == 0)
+          base = __hip_atomic_fetch_add(&ctr->qhead, (unsigned long long)n_take, __ATOMIC_RELAXED,
+                                        __HIP_MEMORY_SCOPE_AGENT);
+        base = __shfl(base, __builtin_ctzll(m_want));
+        if (want && rk < n_take) claim = base + rk;
+      }
+    }
+    if (take) {
+      load_elec_tail<R, kBanded, kField>(G, T, F, P, e);
+      has = true;
+    } else if (!has && !done && claim != kNone) {
+      if (claim < S.capacity && ld_coh_int(&S.qready[claim]) == epoch) {
+        slot = ld_coh_int(&S.qslot[claim]);
+        e.x = ld_coh(&S.x0[slot]); e.y = ld_coh(&S.y0[slot]); e.z = ld_coh(&S.z0[slot]);
+        e.t = ld_coh(&S.t0[slot]);
+        e.vx = (R)ld_coh(&S.vx0[slot]); e.vy = (R)ld_coh(&S.vy0[slot]);
+        e.vz = (R)ld_coh(&S.vz0[slot]);
+        e.eid = ld_coh_int(&S.eid[slot]);
+        e.aval = ld_coh_int(&S.aval[slot]);
+        load_elec_tail<R, kBanded, kField>(G, T, F, P, e);
+        has = true;
+        claim = kNone;
+      }
+    }
+    if (!has && !done && ld_coh_int(&ctr->live) == 0) done = true;
+    if (__ballot(!done) == 0) break;
+    if (__ballot(has) == 0) __builtin_amdgcn_s_sleep(2);
   }
 }
 
@@ -421,77 +599,133 @@ hipError_t launch_reset(Counters* ctr, uint64_t n_prim, AvalStats* stats, uint32
   return hipGetLastError();
 }
 
-hipError_t launch_load_primaries(const PrimaryRec* prim, uint64_t n, const Store& S, uint32_t epoch,
-                                 double k_a, uint32_t n_aval, uint32_t* active, Counters* ctr,
-                                 int plain, hipStream_t st) {
+hipError_t launch_load_primaries(const PrimaryRec* prim, uint64_t n, const Store& S, double k_a,
+                                 uint32_t n_aval, uint32_t* active, Counters* ctr, int plain,
+                                 hipStream_t st) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_load_primaries, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0,
-                     st, prim, n, S, epoch, k_a, n_aval, active, ctr, plain);
+                     st, prim, n, S, k_a, n_aval, active, ctr, plain);
   return hipGetLastError();
 }
 
-template <bool B, int FK>
+template <class R, bool B, int FK>
 static void gen_one(const GasDev& G, const FieldDev& F, const RunParams& P, const Store& S,
                     const uint32_t* active, uint32_t n_active, uint32_t* next, Counters* ctr,
                     hipStream_t st) {
-  hipLaunchKernelGGL((k_generation<B, FK>), dim3((n_active + kBlock - 1) / kBlock), dim3(kBlock), 0,
-                     st, G, F, P, S, active, n_active, next, ctr);
+  hipLaunchKernelGGL((k_generation<R, B, FK>), dim3((n_active + kBlock - 1) / kBlock), dim3(kBlock),
+                     0, st, G, F, P, S, active, n_active, next, ctr);
 }
 
-hipError_t launch_generation(int banded, int field_kind, const GasDev& G, const FieldDev& F,
-                             const RunParams& P, const Store& S, const uint32_t* active,
-                             uint32_t n_active, uint32_t* next, Counters* ctr, hipStream_t st) {
-  if (n_active == 0) return hipSuccess;
+template <class R>
+static void gen_prec(int banded, int fk, const GasDev& G, const FieldDev& F, const RunParams& P,
+                     const Store& S, const uint32_t* active, uint32_t n_active, uint32_t* next,
+                     Counters* ctr, hipStream_t st) {
   if (banded) {
-    if (field_kind == FIELD_SLAB)
-      gen_one<true, FIELD_SLAB>(G, F, P, S, active, n_active, next, ctr, st);
+    if (fk == FIELD_SLAB)
+      gen_one<R, true, FIELD_SLAB>(G, F, P, S, active, n_active, next, ctr, st);
     else
-      gen_one<true, FIELD_POLAR>(G, F, P, S, active, n_active, next, ctr, st);
+      gen_one<R, true, FIELD_POLAR>(G, F, P, S, active, n_active, next, ctr, st);
   } else {
-    if (field_kind == FIELD_SLAB)
-      gen_one<false, FIELD_SLAB>(G, F, P, S, active, n_active, next, ctr, st);
+    if (fk == FIELD_SLAB)
+      gen_one<R, false, FIELD_SLAB>(G, F, P, S, active, n_active, next, ctr, st);
     else
-      gen_one<false, FIELD_POLAR>(G, F, P, S, active, n_active, next, ctr, st);
+      gen_one<R, false, FIELD_POLAR>(G, F, P, S, active, n_active, next, ctr, st);
   }
+}
+
+hipError_t launch_generation(int fp32, int banded, int field_kind, const GasDev& G,
+                             const FieldDev& F, const RunParams& P, const Store& S,
+                             const uint32_t* active, uint32_t n_active, uint32_t* next,
+                             Counters* ctr, hipStream_t st) {
+  if (n_active == 0) return hipSuccess;
+  if (fp32)
+    gen_prec<float>(banded, field_kind, G, F, P, S, active, n_active, next, ctr, st);
+  else
+    gen_prec<double>(banded, field_kind, G, F, P, S, active, n_active, next, ctr, st);
   return hipGetLastError();
 }
 
-template <bool B, int FK>
-static const void* persistent_fn() {
-  return reinterpret_cast<const void*>(&k_persistent<B, FK>);
+template <class R>
+static const void* pick_persistent_prec(int banded, int fk) {
+  if (banded)
+    return fk == FIELD_SLAB ? reinterpret_cast<const void*>(&k_persistent<R, true, FIELD_SLAB>)
+                            : reinterpret_cast<const void*>(&k_persistent<R, true, FIELD_POLAR>);
+  return fk == FIELD_SLAB ? reinterpret_cast<const void*>(&k_persistent<R, false, FIELD_SLAB>)
+                          : reinterpret_cast<const void*>(&k_persistent<R, false, FIELD_POLAR>);
 }
 
-static const void* pick_persistent(int banded, int field_kind) {
-  if (banded) return field_kind == FIELD_SLAB ? persistent_fn<true, FIELD_SLAB>() : persistent_fn<true, FIELD_POLAR>();
-  return field_kind == FIELD_SLAB ? persistent_fn<false, FIELD_SLAB>() : persistent_fn<false, FIELD_POLAR>();
+hipError_t persistent_occupancy(int fp32, int banded, int field_kind, int block,
+                                int* blocks_per_cu) {
+  const void* fn = fp32 ? pick_persistent_prec<float>(banded, field_kind)
+                        : pick_persistent_prec<double>(banded, field_kind);
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, block, 0);
 }
 
-hipError_t persistent_occupancy(int banded, int field_kind, int block, int* blocks_per_cu) {
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, pick_persistent(banded, field_kind),
-                                                      block, 0);
-}
-
-template <bool B, int FK>
+template <class R, bool B, int FK>
 static void pers_one(const GasDev& G, const FieldDev& F, const RunParams& P, const Store& S,
-                     Counters* ctr, uint32_t epoch, int fpp, int grid, int block, hipStream_t st) {
-  hipLaunchKernelGGL((k_persistent<B, FK>), dim3(grid), dim3(block), 0, st, G, F, P, S, ctr, epoch,
-                     fpp);
+                     Counters* ctr, int fpp, int grid, int block, hipStream_t st) {
+  hipLaunchKernelGGL((k_persistent<R, B, FK>), dim3(grid), dim3(block), 0, st, G, F, P, S, ctr, fpp);
 }
 
-hipError_t launch_persistent(int banded, int field_kind, const GasDev& G, const FieldDev& F,
-                             const RunParams& P, const Store& S, Counters* ctr, uint32_t epoch,
-                             int flights_per_pass, int grid, int block, hipStream_t st) {
+template <class R>
+static void pers_prec(int banded, int fk, const GasDev& G, const FieldDev& F, const RunParams& P,
+                      const Store& S, Counters* ctr, int fpp, int grid, int block, hipStream_t st) {
   if (banded) {
-    if (field_kind == FIELD_SLAB)
-      pers_one<true, FIELD_SLAB>(G, F, P, S, ctr, epoch, flights_per_pass, grid, block, st);
+    if (fk == FIELD_SLAB)
+      pers_one<R, true, FIELD_SLAB>(G, F, P, S, ctr, fpp, grid, block, st);
     else
-      pers_one<true, FIELD_POLAR>(G, F, P, S, ctr, epoch, flights_per_pass, grid, block, st);
+      pers_one<R, true, FIELD_POLAR>(G, F, P, S, ctr, fpp, grid, block, st);
   } else {
-    if (field_kind == FIELD_SLAB)
-      pers_one<false, FIELD_SLAB>(G, F, P, S, ctr, epoch, flights_per_pass, grid, block, st);
+    if (fk == FIELD_SLAB)
+      pers_one<R, false, FIELD_SLAB>(G, F, P, S, ctr, fpp, grid, block, st);
     else
-      pers_one<false, FIELD_POLAR>(G, F, P, S, ctr, epoch, flights_per_pass, grid, block, st);
+      pers_one<R, false, FIELD_POLAR>(G, F, P, S, ctr, fpp, grid, block, st);
   }
+}
+
+hipError_t launch_persistent(int fp32, int banded, int field_kind, const GasDev& G,
+                             const FieldDev& F, const RunParams& P, const Store& S, Counters* ctr,
+                             int flights_per_pass, int grid, int block, hipStream_t st) {
+  if (fp32)
+    pers_prec<float>(banded, field_kind, G, F, P, S, ctr, flights_per_pass, grid, block, st);
+  else
+    pers_prec<double>(banded, field_kind, G, F, P, S, ctr, flights_per_pass, grid, block, st);
+  return hipGetLastError();
+}
+
+// FP32 copies of the rate tables: rates rounded to nearest, majorants
+// rounded up and band edges rounded down (so they stay bounds), inverse
+// majorants from the rounded-up values.
+__global__ void k_tables_f32(const double* __restrict__ cum, const double* __restrict__ total,
+                             const double* __restrict__ cum0, size_t n_cum, int n_nodes,
+                             const double* __restrict__ bg, const double* __restrict__ be, int n_bands,
+                             float* __restrict__ cum_f, float* __restrict__ total_f,
+                             float* __restrict__ cum0_f, float* __restrict__ bg_f,
+                             float* __restrict__ bi_f, float* __restrict__ be_f) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n_cum) cum_f[i] = (float)cum[i];
+  if (i < (size_t)n_nodes) {
+    total_f[i] = (float)total[i];
+    cum0_f[i] = (float)cum0[i];
+  }
+  if (i < (size_t)n_bands) {
+    const float g = __double2float_ru(bg[i]);
+    bg_f[i] = g;
+    bi_f[i] = 1.0f / g;
+    be_f[i] = __double2float_rd(be[i]);
+  }
+}
+
+hipError_t launch_tables_f32(const double* cum, const double* total, const double* cum0,
+                             size_t n_cum, int n_nodes, const double* bg, const double* be,
+                             int n_bands, float* cum_f, float* total_f, float* cum0_f, float* bg_f,
+                             float* bi_f, float* be_f, hipStream_t st) {
+  size_t n = n_cum;
+  if ((size_t)n_nodes > n) n = n_nodes;
+  if ((size_t)n_bands > n) n = n_bands;
+  hipLaunchKernelGGL(k_tables_f32, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, st,
+                     cum, total, cum0, n_cum, n_nodes, bg, be, n_bands, cum_f, total_f, cum0_f, bg_f,
+                     bi_f, be_f);
   return hipGetLastError();
 }
 

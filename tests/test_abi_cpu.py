@@ -48,7 +48,7 @@ def test_abi_version_and_sizes(A):
     assert A.ENDPOINT_DTYPE.itemsize == 128
     assert W.PRIMARY_DTYPE.itemsize == 72
     assert C.sizeof(A._Counts) == 8 * 18 + 8
-    assert C.sizeof(A._Opts) == 64
+    assert C.sizeof(A._Opts) == 72
 
 
 def test_argument_errors_without_a_device(A):

@@ -207,3 +207,30 @@ def test_torch_device_primaries_and_stream(A, oracle_mod):
     ep = r.endpoints()
     ep = ep[np.lexsort((ep["eid"], ep["aval"]))]
     CMP.assert_parity(ep, ref)
+
+
+def test_graph_replays_match_eager(A):
+    """The batched run captured into a HIP graph and replayed four times,
+    with eager runs and host synchronisation in between: every replay gives
+    the eager endpoints bit for bit (FP64 and FP32-mixed)."""
+    wl = W.argon(64, band_bins=100)
+    g = A.Gas(wl.gas)
+    f = A.Field(wl.field)
+    for prec in (A.FP64, A.FP32_MIXED):
+        eager = A.Run(g, f, wl.primaries, wl.n_aval, seed=wl.seed, majorant=A.BANDED, precision=prec,
+                      capacity=1_000_000)
+        eager.execute(); eager.sync()
+        ref = eager.endpoints()
+        ref = ref[np.lexsort((ref["eid"], ref["aval"]))]
+        rc = eager.counts()
+        gr = A.Run(g, f, wl.primaries, wl.n_aval, seed=wl.seed, majorant=A.BANDED, precision=prec,
+                   capacity=1_000_000, graph=True)
+        for rep in range(4):
+            gr.execute(); gr.sync()
+            ep = gr.endpoints()
+            ep = ep[np.lexsort((ep["eid"], ep["aval"]))]
+            assert ep.tobytes() == ref.tobytes(), f"replay {rep}"
+            assert gr.counts() == rc
+            eager.execute(); eager.sync()  # eager work between replays
+        gr.close()
+        eager.close()
