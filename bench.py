@@ -9,8 +9,8 @@ resident in HBM.  Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
-import math
 import os
 import sys
 import time
@@ -28,6 +28,74 @@ OPS_PER_REAL = 220
 OPS_PER_ION = 280
 PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 
+# HBM traffic of the transport kernel from two counter passes (FETCH_SIZE,
+# WRITE_SIZE per dispatch), valid only for the kernel sources it was taken on.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_persistent_argon1000_fp64_banded.json")
+KERNEL_SOURCES = ("paper_2509_15377_amd/csrc/avm_kernels.hip",
+                  "paper_2509_15377_amd/csrc/avm_device.hpp",
+                  "paper_2509_15377_amd/csrc/avm_internal.hpp")
+
+
+def kernel_source_digest():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch of the headline kernel, or None when the counters
+    were taken on other kernel sources (or never)."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_sha256") != kernel_source_digest():
+        return None
+    return (t["fetch_kib_per_dispatch"] * t["fetch_scale"]
+            + t["write_kib_per_dispatch"] * t["write_scale"]) * 1024.0
+
+
+def copy_probe():
+    """A plain device copy of known size, for scaling the HBM byte counters
+    (run under rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE)."""
+    import torch
+    n = 1 << 28
+    a = torch.ones(n, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n}), flush=True)
+
+
+def side_legs(args, make, timed, paths, gas, field, wl, capacity, stream):
+    """The majorant lever on its own (same batched kernel, global majorant),
+    and the headline path with primaries handed over in host memory (their
+    copy to HBM then sits inside every step)."""
+    from paper_2509_15377_amd import avm
+    gr = make(avm.BATCHED, avm.GLOBAL, graph=not args.eager)
+    gw, gk = timed(gr)
+    gc = gr.counts()
+    gms = gw * 1e3 / args.steps
+    gfl = gc["n_real"] + gc["n_null"] + gc["n_masked"]
+    paths["batched_fp64_global"] = {
+        "real_collisions_per_s": gc["n_real"] / (gms * 1e-3),
+        "secondaries_per_s": gc["n_ion"] / (gms * 1e-3),
+        "flights_per_s": gfl / (gms * 1e-3),
+        "ms_per_step": gms, "kernel_ms": sum(gk) / len(gk),
+        "null_fraction": (gc["n_null"] + gc["n_masked"]) / max(gfl, 1)}
+    gr.close()
+    hr = avm.Run(gas, field, wl.primaries, wl.n_aval, seed=wl.seed, majorant=avm.BANDED,
+                 mode=avm.BATCHED, capacity=capacity, timeout_s=300.0, stream=stream)
+    hw, _ = timed(hr)
+    hms = hw * 1e3 / args.steps
+    paths["batched_fp64_banded_host_primaries"] = {
+        "real_collisions_per_s": hr.counts()["n_real"] / (hms * 1e-3), "ms_per_step": hms}
+    hr.close()
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -40,6 +108,10 @@ def parse():
     ap.add_argument("--no-mixed", action="store_true", help="skip the FP32-mixed leg")
     ap.add_argument("--eager", action="store_true",
                     help="launch the batched run eagerly instead of replaying its HIP graph")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="time only the headline path (for counter passes)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a 1 GiB device copy (counter calibration)")
     return ap.parse_args()
 
 
@@ -49,6 +121,11 @@ def main():
         print(f"bench.py runs on exactly one GPU: this build has no multi-GPU path "
               f"(--gpus {args.gpus} requested)", file=sys.stderr)
         sys.exit(2)
+    if args.copy_probe:
+        copy_probe()
+        return
+    if args.headline_only:
+        args.no_mixed = args.no_plain = args.no_cpu = True
     import numpy as np
     import torch
 
@@ -114,6 +191,8 @@ def main():
             "ms_per_step": mms, "kernel_ms": sum(mk) / len(mk),
             "mean_gain": mc["n_endpoints"] / wl.n_aval, "graph": use_graph}
         mr.close()
+    if not args.headline_only:
+        side_legs(args, make, timed, paths, gas, field, wl, capacity, stream)
     if not args.no_plain:
         # the paper's scheduling (one kernel per transport iteration, host
         # reads the active count back) with the global majorant, one pass
@@ -133,19 +212,25 @@ def main():
 
     cpu = None
     if not args.no_cpu:
+        # the oracle on the host cores: the whole workload on every core,
+        # and every 20th avalanche on one thread
         from oracle import oracle as O
-        idx = W.subset_primaries(wl.primaries, 4)
-        og = O.Gas(wl.gas)
+        og = O.Gas(wl.gas, band_bins=band_bins)
         of = O.Field(wl.field)
         t2 = time.perf_counter()
-        ep, threads = O.run(og, of, wl.primaries[idx], wl.seed, banded=True, ids=idx,
-                            return_threads=True)
+        ep, threads = O.run(og, of, wl.primaries, wl.seed, banded=True, return_threads=True)
         tc = time.perf_counter() - t2
+        idx = W.subset_primaries(wl.primaries, 20)
+        t3 = time.perf_counter()
+        ep1 = O.run(og, of, wl.primaries[idx], wl.seed, banded=True, ids=idx, threads=1)
+        t1c = time.perf_counter() - t3
         cpu = {"value": float(ep["n_real"].sum() / tc), "unit": "real collisions/s",
                "cores": int(threads), "kind": "oracle",
-               "sample": f"avalanches with id % 4 == 0 ({idx.size} of {wl.n_aval}), "
-                         f"banded majorant, FP64, {tc:.1f} s",
-               "secondaries_per_s": float(ep["n_ion"].sum() / tc)}
+               "sample": f"all {wl.n_aval} avalanches, banded majorant, FP64, {tc:.1f} s "
+                         f"on {threads} threads",
+               "secondaries_per_s": float(ep["n_ion"].sum() / tc),
+               "single_thread": {"value": float(ep1["n_real"].sum() / t1c),
+                                 "sample": f"avalanches with id % 20 == 0 ({idx.size}), {t1c:.1f} s"}}
 
     line = {
         "metric": "electron real collisions/s (secondaries/s alongside) at gain ~1e3",
@@ -169,7 +254,7 @@ def main():
         "null_fraction": (c["n_null"] + c["n_masked"]) / max(flights, 1),
         "paths": paths,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_LANE_OPS,
-                     "unit": "lane-ops/s", "frac": achieved / PEAK_LANE_OPS, "traffic": None,
+                     "unit": "lane-ops/s", "frac": achieved / PEAK_LANE_OPS, "traffic": measured_traffic(),
                      "kernel": "k_persistent<banded,slab>", "kernel_ms": k_ms,
                      "ops_per_launch": ops},
         "cpu_baseline": cpu,
