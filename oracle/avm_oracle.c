@@ -684,7 +684,59 @@ typedef struct {
   const orc_gas* g;
   const orc_field* f;
   const orc_opts* o;
+  const orc_signal* sig; /* NULL: no induced signal */
 } ctx_t;
+
+/* ---- induced signal (Shockley-Ramo, readout electrode as in the header) -- */
+double orc_weighting(const orc_field* f, const double r[3])
+{
+  if (f->kind == FIELD_SLAB) return (r[2] - f->z_lo) / (f->z_hi - f->z_lo);
+  return log(f->b / sqrt(r[0] * r[0] + r[1] * r[1])) / log(f->b / f->a);
+}
+
+static double edge_time(const orc_signal* s, int64_t j) { return s->t0_ns + (double)j * s->dt_ns; }
+
+/* Index of the first bin edge strictly after t; edges beyond T_n_bins are
+ * irrelevant, so the answer is capped at n_bins + 1. */
+static int64_t first_edge_after(const orc_signal* s, double t)
+{
+  if (t < edge_time(s, 0)) return 0;
+  if (!(t < edge_time(s, s->n_bins))) return (int64_t)s->n_bins + 1;
+  int64_t j = (int64_t)floor((t - s->t0_ns) / s->dt_ns) + 1;
+  if (j < 1) j = 1;
+  if (j > s->n_bins) j = s->n_bins;
+  while (!(edge_time(s, j) > t)) j++;
+  while (j > 0 && edge_time(s, j - 1) > t) j--;
+  return j;
+}
+
+static void deposit(const orc_signal* s, uint32_t aval, int64_t bin, double dq)
+{
+  if (bin >= 0 && bin < s->n_bins) s->out[(size_t)aval * (size_t)s->n_bins + (size_t)bin] += dq;
+}
+
+/* The flight from (r_s, v_s) at time t_s, in the frozen field E, ends at
+ * r_e at time t_e: it is cut at every bin edge T in (t_s, t_e], the
+ * position at T coming from the flight formula, and each piece adds the
+ * change of the weighting potential over it to its bin. */
+static void signal_flight(const ctx_t* cx, uint32_t aval, const double r_s[3], const double v_s[3],
+                          const double E[3], double t_s, double t_e, const double r_e[3])
+{
+  const orc_signal* s = cx->sig;
+  if (!s) return;
+  double phi_a = orc_weighting(cx->f, r_s);
+  int64_t j = first_edge_after(s, t_s);
+  while (j <= s->n_bins && edge_time(s, j) <= t_e) {
+    double T = edge_time(s, j);
+    double rr[3], vv[3];
+    orc_propagate(r_s, v_s, E, cx->f->B, T - t_s, rr, vv);
+    double phi_b = orc_weighting(cx->f, rr);
+    deposit(s, aval, j - 1, phi_b - phi_a);
+    phi_a = phi_b;
+    j++;
+  }
+  deposit(s, aval, j - 1, orc_weighting(cx->f, r_e) - phi_a);
+}
 
 static double energy_of(const double v[3]) { return dot3(v, v) / (2.0 * orc_k_a()); }
 
@@ -813,6 +865,7 @@ static int transport(const ctx_t* cx, elec e, estack* st, orc_endpoint* ep)
       }
     }
     if (side) {
+      signal_flight(cx, e.aval, e.r, e.v, E, e.t, e.t + s_exit, rn);
       e.r[0] = rn[0]; e.r[1] = rn[1]; e.r[2] = rn[2];
       e.v[0] = vn[0]; e.v[1] = vn[1]; e.v[2] = vn[2];
       e.t = e.t + s_exit;
@@ -820,6 +873,7 @@ static int transport(const ctx_t* cx, elec e, estack* st, orc_endpoint* ep)
       break;
     }
     orc_propagate(e.r, e.v, E, f->B, tau_end, rn, vn);
+    signal_flight(cx, e.aval, e.r, e.v, E, e.t, e.t + tau_end, rn);
     e.r[0] = rn[0]; e.r[1] = rn[1]; e.r[2] = rn[2];
     e.v[0] = vn[0]; e.v[1] = vn[1]; e.v[2] = vn[2];
     e.t = e.t + tau_end;
@@ -1020,14 +1074,27 @@ static int cmp_u64_by_aval(const void* a, const void* b, void* arg)
 int orc_run(const orc_gas* g, const orc_field* f, const orc_primary* prim, const uint64_t* ids,
             uint64_t n_prim, const orc_opts* o, orc_result** out, int32_t* threads_used)
 {
+  return orc_run_signal(g, f, prim, ids, n_prim, o, NULL, out, threads_used);
+}
+
+int orc_run_signal(const orc_gas* g, const orc_field* f, const orc_primary* prim, const uint64_t* ids,
+                   uint64_t n_prim, const orc_opts* o, const orc_signal* sig, orc_result** out,
+                   int32_t* threads_used)
+{
   if (!g || !f || !o || !out || (!prim && n_prim)) return ORC_E_ARG;
+  if (sig) {
+    if (sig->n_bins < 1 || !(sig->dt_ns > 0.0) || !isfinite(sig->dt_ns) || !isfinite(sig->t0_ns) || !sig->out)
+      return ORC_E_ARG;
+    for (uint64_t i = 0; i < n_prim; ++i)
+      if (prim[i].aval >= sig->n_rows) return ORC_E_ARG;
+  }
   if (o->k_max > (1u << 30) - 1u) return ORC_E_ARG;
   if (o->banded && f->B[0] * f->B[0] + f->B[1] * f->B[1] + f->B[2] * f->B[2] != 0.0)
     return ORC_E_ARG; /* the band bound needs a convex energy along the flight */
   if (f->kind == FIELD_SLAB && f->n_E > 1)
     for (uint64_t i = 0; i < n_prim; ++i)
       if (prim[i].aval >= f->n_E) return ORC_E_ARG;
-  ctx_t cx = {g, f, o};
+  ctx_t cx = {g, f, o, sig};
   uint64_t* order = malloc(sizeof(uint64_t) * (n_prim ? n_prim : 1));
   uint64_t* goff = malloc(sizeof(uint64_t) * (n_prim + 1));
   if (!order || !goff) {

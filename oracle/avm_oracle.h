@@ -114,6 +114,34 @@ typedef struct orc_result orc_result;
  * ids[i] = i).  Endpoints are returned grouped by avalanche. */
 int orc_run(const orc_gas*, const orc_field*, const orc_primary* prim, const uint64_t* ids,
             uint64_t n_prim, const orc_opts*, orc_result** out, int32_t* threads_used);
+
+/* Induced signal on the readout electrode (the step after transport, paper
+ * Sec. 3.2: induced signals are read out as usual once the avalanche is
+ * simulated).  Shockley-Ramo: a point charge q at r induces -q phi_w(r) on
+ * the electrode whose weighting potential is phi_w, so moving from r to r'
+ * changes the induced charge by -q [phi_w(r') - phi_w(r)].  Readout
+ * electrode: the z_hi plane of a slab, phi_w = (z - z_lo) / (z_hi - z_lo);
+ * the wire of the coaxial geometry, phi_w = ln(b/rho) / ln(b/a).  Bin j
+ * covers [T_j, T_j+1) with T_j = t0 + j dt; out[a n_bins + j] receives the
+ * change of induced charge during bin j, in units of the elementary charge,
+ * from the electrons (q = -1) of avalanche a: the sum of
+ * phi_w(r(T_j+1)) - phi_w(r(T_j)) over them, each electron's times clamped
+ * to its own lifetime (its motion before birth and after termination
+ * contributes nothing).  Ions are not transported.  `out` holds
+ * n_rows x n_bins values, n_rows > every avalanche id; it is accumulated
+ * into (zero it first). */
+typedef struct {
+  double t0_ns, dt_ns;
+  int32_t n_bins;
+  uint32_t n_rows;
+  double* out;
+} orc_signal;
+
+int orc_run_signal(const orc_gas*, const orc_field*, const orc_primary* prim, const uint64_t* ids,
+                   uint64_t n_prim, const orc_opts*, const orc_signal* sig, orc_result** out,
+                   int32_t* threads_used);
+/* Weighting potential of the readout electrode at r (see above). */
+double orc_weighting(const orc_field*, const double r[3]);
 uint64_t orc_result_count(const orc_result*);
 int orc_result_copy(const orc_result*, orc_endpoint* out);
 void orc_result_destroy(orc_result*);

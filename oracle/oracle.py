@@ -53,6 +53,11 @@ class _Opts(C.Structure):
                 ("t_max_ns", C.c_double), ("k_max", C.c_uint32), ("n_threads", C.c_int32)]
 
 
+class _Signal(C.Structure):
+    _fields_ = [("t0_ns", C.c_double), ("dt_ns", C.c_double), ("n_bins", C.c_int32),
+                ("n_rows", C.c_uint32), ("out", C.POINTER(C.c_double))]
+
+
 _lib = None
 
 
@@ -82,6 +87,11 @@ def lib():
         L.orc_field_eval.argtypes = [vp, dp, C.c_uint32, dp]
         L.orc_run.argtypes = [vp, vp, vp, C.POINTER(C.c_uint64), C.c_uint64, C.POINTER(_Opts),
                               C.POINTER(vp), C.POINTER(C.c_int32)]
+        L.orc_run_signal.argtypes = [vp, vp, vp, C.POINTER(C.c_uint64), C.c_uint64,
+                                     C.POINTER(_Opts), C.POINTER(_Signal), C.POINTER(vp),
+                                     C.POINTER(C.c_int32)]
+        L.orc_weighting.argtypes = [vp, dp]
+        L.orc_weighting.restype = C.c_double
         L.orc_result_count.argtypes = [vp]
         L.orc_result_count.restype = C.c_uint64
         L.orc_result_copy.argtypes = [vp, vp]
@@ -202,6 +212,11 @@ class Field:
             lib().orc_field_destroy(self.h)
             self.h = None
 
+    def weighting(self, r):
+        """Weighting potential of the readout electrode at r (orc_weighting)."""
+        rr = np.ascontiguousarray(r, dtype=np.float64)
+        return lib().orc_weighting(self.h, _dptr(rr))
+
     def eval(self, r, aval=0):
         r = np.ascontiguousarray(r, dtype=np.float64)
         E = np.zeros(3)
@@ -210,12 +225,14 @@ class Field:
 
 
 def run(gas, field, primaries, seed, *, banded=False, fifo=False, t_max=math.inf,
-        k_max=K_MAX_DEFAULT, threads=0, ids=None, return_threads=False):
+        k_max=K_MAX_DEFAULT, threads=0, ids=None, return_threads=False, signal=None):
     """Transport the primaries; returns endpoints sorted by (aval, eid).
 
     ``gas``/``field`` are oracle ``Gas``/``Field`` objects or workload
     descriptions (built on the fly).  ``ids`` gives the primary ids used for
-    the electron ids (default: array positions)."""
+    the electron ids (default: array positions).  ``signal=(t0_ns, dt_ns,
+    n_bins, n_rows)`` also returns the induced-signal array [n_rows, n_bins]
+    (see orc_run_signal): the result is then (endpoints, signal)."""
     L = lib()
     g = gas if isinstance(gas, Gas) else Gas(gas)
     f = field if isinstance(field, Field) else Field(field)
@@ -229,8 +246,14 @@ def run(gas, field, primaries, seed, *, banded=False, fifo=False, t_max=math.inf
     o = _Opts(int(seed), int(bool(banded)), int(bool(fifo)), float(t_max), int(k_max), int(threads))
     h = C.c_void_p()
     used = C.c_int32()
-    rc = L.orc_run(g.h, f.h, prim.ctypes.data_as(C.c_void_p), idp, prim.size, C.byref(o),
-                   C.byref(h), C.byref(used))
+    sig = None
+    sp = None
+    if signal is not None:
+        t0, dt, nb, nr = signal
+        sig = np.zeros((int(nr), int(nb)))
+        sp = C.byref(_Signal(float(t0), float(dt), int(nb), int(nr), _dptr(sig)))
+    rc = L.orc_run_signal(g.h, f.h, prim.ctypes.data_as(C.c_void_p), idp, prim.size, C.byref(o),
+                          sp, C.byref(h), C.byref(used))
     if rc:
         raise ValueError(f"orc_run failed ({rc})")
     n = L.orc_result_count(h)
@@ -239,9 +262,10 @@ def run(gas, field, primaries, seed, *, banded=False, fifo=False, t_max=math.inf
         L.orc_result_copy(h, out.ctypes.data_as(C.c_void_p))
     L.orc_result_destroy(h)
     out = out[np.lexsort((out["eid"], out["aval"]))]
+    res = out if sig is None else (out, sig)
     if return_threads:
-        return out, used.value
-    return out
+        return res, used.value
+    return res
 
 
 def per_avalanche(ep, n_aval):
