@@ -95,6 +95,15 @@ def side_legs(args, make, timed, paths, gas, field, wl, capacity, stream):
     paths["batched_fp64_banded_host_primaries"] = {
         "real_collisions_per_s": hr.counts()["n_real"] / (hms * 1e-3), "ms_per_step": hms}
     hr.close()
+    # the headline path with the induced signal on (240 bins of 5 ps)
+    sr = make(avm.BATCHED, avm.BANDED, graph=not args.eager)
+    sr.set_signal(0.0, 0.005, 240)
+    sw, sk = timed(sr)
+    sms = sw * 1e3 / args.steps
+    paths["batched_fp64_banded_signal"] = {
+        "real_collisions_per_s": sr.counts()["n_real"] / (sms * 1e-3), "ms_per_step": sms,
+        "kernel_ms": sum(sk) / len(sk), "signal_bins": 240}
+    sr.close()
 
 
 def parse():

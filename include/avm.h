@@ -102,6 +102,14 @@ avm_status avm_gas_get_info(const avm_gas* gas, avm_gas_info* out);
  * [n_bands] (the last edge is +INFINITY). */
 avm_status avm_gas_get_tables(const avm_gas* gas, double* cumulative, double* band_gamma,
                               double* band_edge_eV);
+/* Rebuild the band majorants with a new band width (band_bins > 0; 0 drops
+ * the bands, leaving the global majorant only).  The per-bin maxima are kept
+ * from avm_gas_create, so the bands are the ones avm_gas_create would build
+ * with this band_bins.  The gas must not be in use by a run that has been
+ * executed and not yet synced; runs created earlier use the new bands from
+ * their next execute (a captured graph is captured again).  Errors:
+ * AVM_E_ARG for band_bins < 0. */
+avm_status avm_gas_set_band_bins(avm_gas* gas, int32_t band_bins);
 void avm_gas_destroy(avm_gas* gas);
 
 /* ------------------------------------------------------------------------ */
@@ -239,6 +247,68 @@ avm_status avm_run_endpoint_arrays(const avm_run* run, avm_endpoint_arrays* out)
  * (plain) or 1 (batched). */
 avm_status avm_run_timing(const avm_run* run, double* transport_ms, uint32_t* iterations);
 void avm_run_destroy(avm_run* run);
+
+/* ------------------------------------------------------------------------ */
+/* Induced signal                                                            */
+/* ------------------------------------------------------------------------ */
+/* Request the induced signal on the readout electrode for the following
+ * executes (paper Sec. 3.2: the induced signal is read out once the
+ * avalanche has been simulated).  Shockley-Ramo: a point charge q at r
+ * induces -q phi_w(r) on an electrode with weighting potential phi_w.
+ * Readout electrode: the z_hi plane of a slab, phi_w = (z - z_lo) /
+ * (z_hi - z_lo); the wire of the coaxial geometry, phi_w = ln(b/rho) /
+ * ln(b/a).  Bin j covers [t0 + j dt, t0 + (j+1) dt); the value of bin j of
+ * avalanche a is the change of induced charge during the bin, in units of
+ * the elementary charge, from the avalanche's electrons (charge -1): the sum
+ * over them of phi_w(r(end of the bin)) - phi_w(r(start of the bin)), each
+ * electron's times clamped to its own life (the position at a bin edge comes
+ * from the flight formula).  Ions are not transported.  Batched mode only
+ * (AVM_E_UNSUPPORTED otherwise); allocates n_aval x n_bins doubles on the
+ * device; the deposits are device atomics, so sums are exact up to the
+ * order of rounding.  Errors: AVM_E_ARG for n_bins < 1, dt <= 0, non-finite
+ * values; AVM_E_STATE while the run executes. */
+avm_status avm_run_set_signal(avm_run* run, double t0_ns, double dt_ns, int32_t n_bins);
+/* Copy the signal rows of avalanches [first, first+n) after avm_run_sync:
+ * out[(a - first) n_bins + j].  AVM_E_STATE without a requested signal or
+ * before sync. */
+avm_status avm_run_signal(const avm_run* run, uint32_t first, uint32_t n, double* out);
+
+/* ------------------------------------------------------------------------ */
+/* Autotuning of the batched launch                                          */
+/* ------------------------------------------------------------------------ */
+#define AVM_TUNE_BANDS 1u /* also choose the gas's band width (banded majorant) */
+
+typedef struct {
+  int32_t flights_per_pass; /* chosen flights between queue visits                     */
+  int32_t waves_per_cu;     /* chosen resident waves per CU (0: occupancy limit)        */
+  int32_t band_bins;        /* band width the gas is left with                          */
+  int32_t trials;           /* configurations timed (0 when taken from the cache)       */
+  int32_t from_cache;       /* 1 when cache_path already held this workload's choice    */
+  int32_t _pad;
+  double best_ms;           /* transport-kernel ms of the chosen configuration (cache:  */
+                            /*   as recorded)                                           */
+  double start_ms;          /* transport-kernel ms of the starting configuration        */
+  uint64_t key;             /* workload key (device, gas table, field, sizes, options)  */
+} avm_tune_result;
+
+/* Choose flights_per_pass, waves_per_cu and (with AVM_TUNE_BANDS and the
+ * banded majorant) the gas's band width for a batched run of these
+ * primaries: a coordinate search over candidate values, each timed on the
+ * device (HIP events around the transport kernel, best of two executions
+ * after one warm-up).  The trials run the given primaries in full, so for a
+ * large workload pass a representative subset.  base: the run options the
+ * result applies to (mode must be AVM_MODE_BATCHED; seed, precision,
+ * majorant, limits, capacity and stream are used as given; graph is
+ * ignored).  cache_path (may be NULL): a text file of earlier choices; a
+ * line with this workload's key is used without trials, a new choice is
+ * appended.  The gas is left with the chosen band width.  Results of runs
+ * depend on the band width (other random draws), not on flights_per_pass or
+ * waves_per_cu.  Errors: AVM_E_ARG as avm_run_create, or a mode other than
+ * batched; any error of the trial runs. */
+avm_status avm_autotune(avm_gas* gas, const avm_field* field, const avm_primary* prim,
+                        int32_t prim_on_device, uint64_t n_prim, uint32_t n_aval,
+                        const avm_run_opts* base, uint32_t flags, const char* cache_path,
+                        avm_tune_result* out);
 
 #ifdef __cplusplus
 }

@@ -68,6 +68,16 @@ class _Counts(C.Structure):
                 ("n_requested", C.c_uint64), ("truncated", C.c_uint32), ("_pad", C.c_uint32)]
 
 
+class _TuneResult(C.Structure):
+    _fields_ = [("flights_per_pass", C.c_int32), ("waves_per_cu", C.c_int32),
+                ("band_bins", C.c_int32), ("trials", C.c_int32), ("from_cache", C.c_int32),
+                ("_pad", C.c_int32), ("best_ms", C.c_double), ("start_ms", C.c_double),
+                ("key", C.c_uint64)]
+
+
+TUNE_BANDS = 1
+
+
 class _EndpointArrays(C.Structure):
     _fields_ = [(n, C.c_void_p) for n in ("x0", "y0", "z0", "t0", "e0", "x1", "y1", "z1", "t1", "e1",
                                           "eid", "parent", "avalanche", "status", "n_real", "n_ion",
@@ -86,6 +96,7 @@ _SIGS = {
                         C.POINTER(_Channel), C.c_int32, C.POINTER(_VP)], C.c_int),
     "avm_gas_get_info": ([_VP, C.POINTER(_GasInfo)], C.c_int),
     "avm_gas_get_tables": ([_VP, _DP, _DP, _DP], C.c_int),
+    "avm_gas_set_band_bins": ([_VP, C.c_int32], C.c_int),
     "avm_gas_destroy": ([_VP], None),
     "avm_field_slab": ([C.c_int32, C.c_double, C.c_double, C.c_uint32, _DP, _DP, C.POINTER(_VP)], C.c_int),
     "avm_field_polar_map": ([C.c_int32, C.c_double, C.c_double, C.c_int32, C.c_int32, _FP, _FP,
@@ -102,6 +113,10 @@ _SIGS = {
     "avm_run_endpoint_arrays": ([_VP, C.POINTER(_EndpointArrays)], C.c_int),
     "avm_run_timing": ([_VP, _DP, C.POINTER(C.c_uint32)], C.c_int),
     "avm_run_destroy": ([_VP], None),
+    "avm_run_set_signal": ([_VP, C.c_double, C.c_double, C.c_int32], C.c_int),
+    "avm_run_signal": ([_VP, C.c_uint32, C.c_uint32, _DP], C.c_int),
+    "avm_autotune": ([_VP, _VP, _VP, C.c_int32, C.c_uint64, C.c_uint32, C.POINTER(_Opts), C.c_uint32,
+                      C.c_char_p, C.POINTER(_TuneResult)], C.c_int),
 }
 EXPORTED = tuple(_SIGS)
 
@@ -172,6 +187,17 @@ class Gas:
         self.n_bands = info.n_bands
         self.band_bins = info.band_bins
 
+    def _refresh(self):
+        info = _GasInfo()
+        _check(lib().avm_gas_get_info(self.h, C.byref(info)))
+        self.n_bands = info.n_bands
+        self.band_bins = info.band_bins
+
+    def set_band_bins(self, band_bins: int):
+        """Rebuild the band majorants with a new band width (avm_gas_set_band_bins)."""
+        _check(lib().avm_gas_set_band_bins(self.h, int(band_bins)), "avm_gas_set_band_bins")
+        self._refresh()
+
     def tables(self):
         cum = np.zeros((self.n_bins + 1, self.n_channels))
         bg = np.zeros(self.n_bands)
@@ -229,6 +255,51 @@ def _counts_dict(c: _Counts):
     return d
 
 
+def _primaries_arg(primaries):
+    """(pointer, on_device, count, object to keep alive) for primary records:
+    a numpy structured array of 72-byte records, or a GPU torch tensor
+    holding them."""
+    if hasattr(primaries, "data_ptr"):  # torch tensor
+        if not primaries.is_cuda:
+            raise ValueError("torch primaries must live on the GPU")
+        if primaries.numel() * primaries.element_size() % 72:
+            raise ValueError("primary tensor size is not a multiple of 72 bytes")
+        return (C.c_void_p(primaries.data_ptr()), 1,
+                primaries.numel() * primaries.element_size() // 72, primaries)
+    p = np.ascontiguousarray(primaries)
+    if p.dtype.itemsize != 72:
+        raise ValueError("primary records must be 72 bytes")
+    return C.c_void_p(p.ctypes.data), 0, p.size, p
+
+
+def _make_opts(seed, precision, majorant, mode, flights_per_pass, t_max, capacity, k_max,
+               waves_per_cu, timeout_s, stream, graph):
+    st = None
+    if stream is not None:
+        st = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+    return _Opts(int(seed), precision, majorant, mode, int(flights_per_pass), float(t_max),
+                 int(capacity), int(k_max), int(waves_per_cu), float(timeout_s), st,
+                 int(bool(graph)), 0)
+
+
+def autotune(gas: Gas, field: Field, primaries, n_aval: int, *, seed: int, precision=FP64,
+             majorant=GLOBAL, capacity=0, t_max=math.inf, k_max=0, timeout_s=0.0, stream=None,
+             tune_bands=True, cache=None):
+    """Choose flights_per_pass, waves_per_cu and (banded) the gas's band
+    width for a batched run of these primaries (avm_autotune).  Returns a
+    dict; pass its flights_per_pass and waves_per_cu to Run."""
+    ptr, on_dev, n_prim, keep = _primaries_arg(primaries)
+    o = _make_opts(seed, precision, majorant, BATCHED, 0, t_max, capacity, k_max, 0, timeout_s,
+                   stream, False)
+    res = _TuneResult()
+    path = None if cache is None else os.fsencode(cache)
+    _check(lib().avm_autotune(gas.h, field.h, ptr, on_dev, n_prim, int(n_aval), C.byref(o),
+                              TUNE_BANDS if tune_bands else 0, path, C.byref(res)), "avm_autotune")
+    del keep
+    gas._refresh()
+    return {k: getattr(res, k) for k, _ in res._fields_ if not k.startswith("_")}
+
+
 class Run:
     """One run (avm_run_*).  ``primaries``: a numpy structured array of
     72-byte primary records (host) or a torch uint8/any tensor on the GPU
@@ -239,27 +310,10 @@ class Run:
                  k_max=0, flights_per_pass=0, waves_per_cu=0, timeout_s=0.0, stream=None,
                  graph=False):
         self._keep = [gas, field, primaries]
-        on_dev = 0
-        if hasattr(primaries, "data_ptr"):  # torch tensor
-            if not primaries.is_cuda:
-                raise ValueError("torch primaries must live on the GPU")
-            if primaries.numel() * primaries.element_size() % 72:
-                raise ValueError("primary tensor size is not a multiple of 72 bytes")
-            n_prim = primaries.numel() * primaries.element_size() // 72
-            ptr = C.c_void_p(primaries.data_ptr())
-            on_dev = 1
-        else:
-            p = np.ascontiguousarray(primaries)
-            if p.dtype.itemsize != 72:
-                raise ValueError("primary records must be 72 bytes")
-            self._keep.append(p)
-            n_prim = p.size
-            ptr = C.c_void_p(p.ctypes.data)
-        st = None
-        if stream is not None:
-            st = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
-        o = _Opts(int(seed), precision, majorant, mode, int(flights_per_pass), float(t_max),
-                  int(capacity), int(k_max), int(waves_per_cu), float(timeout_s), st, int(bool(graph)), 0)
+        ptr, on_dev, n_prim, keep = _primaries_arg(primaries)
+        self._keep.append(keep)
+        o = _make_opts(seed, precision, majorant, mode, flights_per_pass, t_max, capacity, k_max,
+                       waves_per_cu, timeout_s, stream, graph)
         h = _VP()
         _check(lib().avm_run_create(gas.h, field.h, ptr, on_dev, n_prim, int(n_aval), C.byref(o),
                                     C.byref(h)), "avm_run_create")
@@ -307,6 +361,18 @@ class Run:
         _check(lib().avm_run_endpoint_arrays(self.h, C.byref(a)))
         return {name: getattr(a, name) for name, _ in a._fields_}
 
+    def set_signal(self, t0_ns: float, dt_ns: float, n_bins: int):
+        """Request the induced signal on the readout electrode (avm_run_set_signal)."""
+        _check(lib().avm_run_set_signal(self.h, float(t0_ns), float(dt_ns), int(n_bins)),
+               "avm_run_set_signal")
+        self.n_signal_bins = int(n_bins)
+
+    def signal(self):
+        """The induced signal [n_aval, n_bins] of the last execute (avm_run_signal)."""
+        out = np.zeros((self.n_aval, self.n_signal_bins))
+        _check(lib().avm_run_signal(self.h, 0, self.n_aval, out.ctypes.data_as(_DP)), "avm_run_signal")
+        return out
+
     def timing(self):
         ms = C.c_double()
         it = C.c_uint32()
@@ -326,9 +392,10 @@ class Run:
 
 
 def run(workload=None, *, gas=None, field=None, primaries=None, n_aval=None, seed=None,
-        device=0, band_bins=None, sort=True, **kw):
+        device=0, band_bins=None, sort=True, signal=None, **kw):
     """Whole simulation in one call.  Returns (endpoints sorted by
-    (avalanche, eid), totals dict, per-avalanche counts dict)."""
+    (avalanche, eid), totals dict, per-avalanche counts dict), plus the
+    induced signal [n_aval, n_bins] when ``signal=(t0_ns, dt_ns, n_bins)``."""
     if workload is not None:
         gas = gas or workload.gas
         field = field or workload.field
@@ -338,12 +405,17 @@ def run(workload=None, *, gas=None, field=None, primaries=None, n_aval=None, see
     g = gas if isinstance(gas, Gas) else Gas(gas, device, band_bins)
     f = field if isinstance(field, Field) else Field(field, device)
     r = Run(g, f, primaries, n_aval, seed=seed, **kw)
+    if signal is not None:
+        r.set_signal(*signal)
     r.execute()
     r.sync()
     ep = r.endpoints()
     tot = r.counts()
     per = r.avalanche_counts()
+    sig = r.signal() if signal is not None else None
     r.close()
     if sort:
         ep = ep[np.lexsort((ep["eid"], ep["aval"]))]
+    if signal is not None:
+        return ep, tot, per, sig
     return ep, tot, per

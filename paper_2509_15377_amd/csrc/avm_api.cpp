@@ -79,6 +79,8 @@ struct avm_gas {
   float *cum_f = nullptr, *cum0_f = nullptr, *total_f = nullptr, *band_gamma_f = nullptr,
         *band_inv_f = nullptr, *band_edge_f = nullptr;
   ChanP<float>* ch_f = nullptr;
+  double* binmax = nullptr;  // per-bin maxima, kept for rebuilding the bands
+  uint64_t version = 0;      // bumped whenever the device tables change
   GasDev dev{};
 };
 
@@ -102,6 +104,7 @@ struct avm_run {
   PrimaryRec* prim_host = nullptr;  // pinned staging
   void* store_mem = nullptr;
   Store S{};
+  Store* store_dev = nullptr;  // device copy of S (the transport kernels read it there)
   uint32_t *list0 = nullptr, *list1 = nullptr;
   Counters* ctr = nullptr;
   AvalStats* stats = nullptr;
@@ -113,9 +116,12 @@ struct avm_run {
   int executed = 0, synced = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
+  uint64_t graph_version = 0;  // gas version the graph was captured with
+  double* signal = nullptr;     // induced signal [n_aval][n_bins] (avm_run_set_signal)
+  SignalDev sigdev{};
   uint32_t iterations = 0;
   double plain_ms = 0.0;
-  int grid = 0, block = 512;
+  int grid = 0, block = persistent_block();
   int clock_khz = 100000;  // wall_clock64() rate
 };
 
@@ -149,6 +155,7 @@ static void gas_free(avm_gas* g) {
   (void)hipFree(g->band_inv_f);
   (void)hipFree(g->band_edge_f);
   (void)hipFree(g->ch_f);
+  (void)hipFree(g->binmax);
   delete g;
 }
 
@@ -231,13 +238,12 @@ avm_status avm_gas_create(int32_t device, double e_max_eV, int32_t n_bins, doubl
   g->n_ch = n_channels;
   g->band_bins = band_bins;
   g->n_bands = band_bins > 0 ? (n_bins + band_bins - 1) / band_bins : 1;
-  double *d_sig = nullptr, *d_binmax = nullptr, *d_gamma = nullptr;
+  double *d_sig = nullptr, *d_gamma = nullptr;
   int32_t* d_vk = nullptr;
   hipStream_t st = nullptr;
   avm_status rc = AVM_OK;
   auto cleanup = [&]() {
     (void)hipFree(d_sig);
-    (void)hipFree(d_binmax);
     (void)hipFree(d_gamma);
     (void)hipFree(d_vk);
     if (st) (void)hipStreamDestroy(st);
@@ -248,7 +254,7 @@ avm_status avm_gas_create(int32_t device, double e_max_eV, int32_t n_bins, doubl
   };
   bool ok = try_hip(hipStreamCreateWithFlags(&st, hipStreamNonBlocking), "hipStreamCreate") &&
             try_hip(dmalloc(&d_sig, sig.size()), "hipMalloc") && try_hip(dmalloc(&d_vk, n_channels), "hipMalloc") &&
-            try_hip(dmalloc(&d_binmax, (size_t)n_bins), "hipMalloc") && try_hip(dmalloc(&d_gamma, 1), "hipMalloc") &&
+            try_hip(dmalloc(&g->binmax, (size_t)n_bins), "hipMalloc") && try_hip(dmalloc(&d_gamma, 1), "hipMalloc") &&
             try_hip(dmalloc(&g->cum, nn * n_channels), "hipMalloc") && try_hip(dmalloc(&g->total, nn), "hipMalloc") &&
             try_hip(dmalloc(&g->cum0, nn), "hipMalloc") &&
             try_hip(dmalloc(&g->band_gamma, (size_t)g->n_bands), "hipMalloc") &&
@@ -267,8 +273,8 @@ avm_status avm_gas_create(int32_t device, double e_max_eV, int32_t n_bins, doubl
          try_hip(hipMemcpyAsync(g->ch, cd.data(), sizeof(ChanDev) * cd.size(), hipMemcpyHostToDevice, st), "H2D") &&
          try_hip(hipMemcpyAsync(g->ch_f, cf.data(), sizeof(ChanP<float>) * cf.size(), hipMemcpyHostToDevice, st), "H2D") &&
          try_hip(launch_build_rates(d_sig, d_vk, n_channels, n_bins, e_max_eV, density_cm3, k_a(), g->cum,
-                                    g->total, d_binmax, st), "rate-table kernels") &&
-         try_hip(launch_build_bands(d_binmax, n_bins, band_bins, g->n_bands, e_max_eV, g->band_gamma,
+                                    g->total, g->binmax, st), "rate-table kernels") &&
+         try_hip(launch_build_bands(g->binmax, n_bins, band_bins, g->n_bands, e_max_eV, g->band_gamma,
                                     g->band_inv, g->band_edge, d_gamma, st), "band kernels") &&
          // cumulative column 0, contiguous (staged in LDS by the transport)
          try_hip(hipMemcpy2DAsync(g->cum0, sizeof(double), g->cum, sizeof(double) * n_channels,
@@ -306,7 +312,6 @@ avm_status avm_gas_create(int32_t device, double e_max_eV, int32_t n_bins, doubl
   D.n_ch = n_channels;
   D.n_bands = g->n_bands;
   D.band_bins = band_bins;
-  D.ch0 = cd[0];
   D.cum_f = g->cum_f;
   D.cum0_f = g->cum0_f;
   D.total_f = g->total_f;
@@ -314,7 +319,6 @@ avm_status avm_gas_create(int32_t device, double e_max_eV, int32_t n_bins, doubl
   D.band_inv_f = g->band_inv_f;
   D.band_edge_f = g->band_edge_f;
   D.ch_f = g->ch_f;
-  D.ch0_f = cf[0];
   float gf = (float)gamma;
   if ((double)gf < gamma) gf = std::nextafter(gf, INFINITY);  // a majorant stays a majorant
   D.gamma_f = gf;
@@ -344,6 +348,60 @@ avm_status avm_gas_get_tables(const avm_gas* g, double* cumulative, double* band
     HIP_TRY(hipMemcpy(cumulative, g->cum, sizeof(double) * ((size_t)g->n_bins + 1) * g->n_ch, hipMemcpyDeviceToHost));
   if (band_gamma) HIP_TRY(hipMemcpy(band_gamma, g->band_gamma, sizeof(double) * g->n_bands, hipMemcpyDeviceToHost));
   if (band_edge_eV) HIP_TRY(hipMemcpy(band_edge_eV, g->band_edge, sizeof(double) * g->n_bands, hipMemcpyDeviceToHost));
+  return AVM_OK;
+}
+
+avm_status avm_gas_set_band_bins(avm_gas* g, int32_t band_bins) {
+  g_err.clear();
+  if (!g) return fail(AVM_E_ARG, "avm_gas_set_band_bins: gas is NULL");
+  if (band_bins < 0) return fail(AVM_E_ARG, "avm_gas_set_band_bins: band_bins < 0");
+  DeviceGuard dg(g->device);
+  if (dg.err != hipSuccess) return fail(AVM_E_HIP, "hipSetDevice: %s", hipGetErrorString(dg.err));
+  const int32_t nb = band_bins > 0 ? (g->n_bins + band_bins - 1) / band_bins : 1;
+  double *bg = nullptr, *bi = nullptr, *be = nullptr, *gam = nullptr;
+  float *bgf = nullptr, *bif = nullptr, *bef = nullptr;
+  hipStream_t st = nullptr;
+  hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+  if (e == hipSuccess) e = dmalloc(&bg, (size_t)nb);
+  if (e == hipSuccess) e = dmalloc(&bi, (size_t)nb);
+  if (e == hipSuccess) e = dmalloc(&be, (size_t)nb);
+  if (e == hipSuccess) e = dmalloc(&gam, 1);
+  if (e == hipSuccess) e = dmalloc(&bgf, (size_t)nb);
+  if (e == hipSuccess) e = dmalloc(&bif, (size_t)nb);
+  if (e == hipSuccess) e = dmalloc(&bef, (size_t)nb);
+  if (e == hipSuccess) e = launch_build_bands(g->binmax, g->n_bins, band_bins, nb, g->e_max, bg, bi, be, gam, st);
+  if (e == hipSuccess)
+    e = launch_tables_f32(nullptr, nullptr, nullptr, 0, 0, bg, be, nb, nullptr, nullptr, nullptr, bgf, bif, bef, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (st) (void)hipStreamDestroy(st);
+  (void)hipFree(gam);
+  if (e != hipSuccess) {
+    for (void* q : {(void*)bg, (void*)bi, (void*)be, (void*)bgf, (void*)bif, (void*)bef}) (void)hipFree(q);
+    return fail(e == hipErrorOutOfMemory ? AVM_E_NOMEM : AVM_E_HIP, "avm_gas_set_band_bins: %s", hipGetErrorString(e));
+  }
+  for (void* q : {(void*)g->band_gamma, (void*)g->band_inv, (void*)g->band_edge, (void*)g->band_gamma_f,
+                  (void*)g->band_inv_f, (void*)g->band_edge_f})
+    (void)hipFree(q);
+  g->band_gamma = bg;
+  g->band_inv = bi;
+  g->band_edge = be;
+  g->band_gamma_f = bgf;
+  g->band_inv_f = bif;
+  g->band_edge_f = bef;
+  g->band_bins = band_bins;
+  g->n_bands = nb;
+  GasDev& D = g->dev;
+  D.band_gamma = bg;
+  D.band_inv = bi;
+  D.band_edge = be;
+  D.band_gamma_f = bgf;
+  D.band_inv_f = bif;
+  D.band_edge_f = bef;
+  D.n_bands = nb;
+  D.band_bins = band_bins;
+  D.band_scale = band_bins > 0 ? (double)g->n_bins / (g->e_max * (double)band_bins) : 0.0;
+  D.band_scale_f = (float)D.band_scale;
+  g->version += 1;
   return AVM_OK;
 }
 
@@ -479,6 +537,8 @@ void avm_field_destroy(avm_field* f) {
 static void run_free(avm_run* r) {
   if (!r) return;
   (void)hipFree(r->store_mem);
+  (void)hipFree(r->store_dev);
+  (void)hipFree(r->signal);
   (void)hipFree(r->list0);
   (void)hipFree(r->list1);
   (void)hipFree(r->ctr);
@@ -514,6 +574,26 @@ static size_t layout_store(Store& S, char* base, uint64_t cap) {
   take(&S.n_masked, 4); take(&S.n_band, 4); take(&S.n_over, 4);
   S.capacity = cap;
   return off;
+}
+
+// Grid of the persistent kernel: blocks per CU from the occupancy limit,
+// capped by the requested resident waves per CU, times the CU count.
+static hipError_t batched_grid(const avm_run* r, int32_t waves_per_cu, int* grid, int* blocks_per_cu_max) {
+  int per_cu = 0, n_cu = 0, dev = 0;
+  hipError_t e = persistent_occupancy(r->opts.precision == AVM_FP32_MIXED, r->opts.majorant == AVM_MAJORANT_BANDED,
+                                      r->field->dev.kind, r->signal != nullptr, r->block, &per_cu);
+  if (e == hipSuccess) e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return e;
+  if (per_cu < 1) per_cu = 1;
+  if (blocks_per_cu_max) *blocks_per_cu_max = per_cu;
+  const int waves_per_block = r->block / 64;
+  if (waves_per_cu > 0) {
+    const int want = (waves_per_cu + waves_per_block - 1) / waves_per_block;
+    per_cu = want < per_cu ? want : per_cu;
+  }
+  *grid = per_cu * n_cu;
+  return hipSuccess;
 }
 
 avm_status avm_run_create(const avm_gas* gas, const avm_field* field, const avm_primary* prim,
@@ -570,6 +650,8 @@ avm_status avm_run_create(const avm_gas* gas, const avm_field* field, const avm_
   hipError_t e = hipMalloc(&r->store_mem, bytes);
   if (e == hipSuccess) layout_store(r->S, static_cast<char*>(r->store_mem), cap);
   if (e == hipSuccess) e = hipMemset(r->S.qready, 0, sizeof(uint32_t) * cap);
+  if (e == hipSuccess) e = dmalloc(&r->store_dev, 1);
+  if (e == hipSuccess) e = hipMemcpy(r->store_dev, &r->S, sizeof(Store), hipMemcpyHostToDevice);
   if (e == hipSuccess && o.mode == AVM_MODE_PLAIN) e = dmalloc(&r->list0, cap);
   if (e == hipSuccess && o.mode == AVM_MODE_PLAIN) e = dmalloc(&r->list1, cap);
   if (e == hipSuccess) e = dmalloc(&r->ctr, 1);
@@ -592,22 +674,7 @@ avm_status avm_run_create(const avm_gas* gas, const avm_field* field, const avm_
   if (e == hipSuccess) e = hipEventCreate(&r->ev0);
   if (e == hipSuccess) e = hipEventCreate(&r->ev1);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&r->ev_done, hipEventDisableTiming);
-  if (e == hipSuccess && o.mode == AVM_MODE_BATCHED) {
-    int per_cu = 0, n_cu = 0, dev = 0;
-    e = persistent_occupancy(o.precision == AVM_FP32_MIXED, o.majorant == AVM_MAJORANT_BANDED,
-                             field->dev.kind, r->block, &per_cu);
-    if (e == hipSuccess) e = hipGetDevice(&dev);
-    if (e == hipSuccess) e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
-    if (e == hipSuccess) {
-      if (per_cu < 1) per_cu = 1;
-      const int waves_per_block = r->block / 64;
-      if (o.waves_per_cu > 0) {
-        int want = (o.waves_per_cu + waves_per_block - 1) / waves_per_block;
-        per_cu = want < per_cu ? want : per_cu;
-      }
-      r->grid = per_cu * n_cu;
-    }
-  }
+  if (e == hipSuccess && o.mode == AVM_MODE_BATCHED) e = batched_grid(r, o.waves_per_cu, &r->grid, nullptr);
   if (e != hipSuccess) {
     const avm_status st = e == hipErrorOutOfMemory ? AVM_E_NOMEM : AVM_E_HIP;
     run_free(r);
@@ -649,10 +716,12 @@ static avm_status enqueue_batched(avm_run* r, hipStream_t st, bool timed) {
   HIP_TRY(launch_reset(r->ctr, r->n_prim, r->stats, r->n_aval, r->tot, st));
   HIP_TRY(launch_load_primaries(pd, r->n_prim, r->S, k_a(), r->n_aval, r->list0, r->ctr, 0, st));
   const RunParams P = run_params(r);
+  if (r->signal) HIP_TRY(launch_zero(r->signal, (size_t)r->n_aval * (size_t)r->sigdev.n_bins, st));
   if (timed) HIP_TRY(hipEventRecord(r->ev0, st));
   HIP_TRY(launch_persistent(r->opts.precision == AVM_FP32_MIXED, r->opts.majorant == AVM_MAJORANT_BANDED,
-                            r->field->dev.kind, r->gas->dev, r->field->dev, P, r->S, r->ctr,
-                            r->opts.flights_per_pass, r->grid, r->block, st));
+                            r->field->dev.kind, r->gas->dev, r->field->dev, P, r->store_dev, r->ctr,
+                            r->opts.flights_per_pass, r->signal ? &r->sigdev : nullptr, r->grid,
+                            r->block, st));
   if (timed) HIP_TRY(hipEventRecord(r->ev1, st));
   HIP_TRY(launch_stats(r->S, r->ctr, r->stats, r->tot, st));
   HIP_TRY(hipMemcpyAsync(r->tot_host, r->tot, sizeof(Totals), hipMemcpyDeviceToHost, st));
@@ -663,11 +732,20 @@ static avm_status enqueue_batched(avm_run* r, hipStream_t st, bool timed) {
 avm_status avm_run_execute(avm_run* r) {
   g_err.clear();
   if (!r) return fail(AVM_E_ARG, "avm_run_execute: run is NULL");
+  if (r->opts.majorant == AVM_MAJORANT_BANDED && r->gas->n_bands < 2)
+    return fail(AVM_E_STATE, "avm_run_execute: banded majorant but the gas has no bands now");
   DeviceGuard dg(r->gas->device);
   hipStream_t st = r->stream;
   r->executed = 1;
   r->synced = 0;
   if (r->opts.mode == AVM_MODE_BATCHED) {
+    if (r->graph_exec && r->graph_version != r->gas->version) {
+      // the gas tables moved since the capture: capture again
+      (void)hipGraphExecDestroy(r->graph_exec);
+      (void)hipGraphDestroy(r->graph);
+      r->graph_exec = nullptr;
+      r->graph = nullptr;
+    }
     if (!r->opts.graph) {
       avm_status s = enqueue_batched(r, st, true);
       if (s != AVM_OK) return s;
@@ -688,6 +766,7 @@ avm_status avm_run_execute(avm_run* r) {
         }
         if (e2 != hipSuccess) return fail(AVM_E_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e2));
         r->graph = g;
+        r->graph_version = r->gas->version;
         HIP_TRY(hipGraphInstantiate(&r->graph_exec, g, nullptr, nullptr, 0));
       }
       HIP_TRY(hipEventRecord(r->ev0, st));
@@ -719,7 +798,7 @@ avm_status avm_run_execute(avm_run* r) {
   while (n_active > 0) {
     HIP_TRY(hipMemsetAsync(&r->ctr->next, 0, sizeof(unsigned long long), st));
     HIP_TRY(hipEventRecord(r->ev0, st));
-    HIP_TRY(launch_generation(fp32, banded, fk, r->gas->dev, r->field->dev, P, r->S, A, (uint32_t)n_active, B, r->ctr, st));
+    HIP_TRY(launch_generation(fp32, banded, fk, r->gas->dev, r->field->dev, P, r->store_dev, A, (uint32_t)n_active, B, r->ctr, st));
     HIP_TRY(hipEventRecord(r->ev1, st));
     HIP_TRY(hipMemcpyAsync(r->ctr_host, r->ctr, sizeof(Counters), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
@@ -866,6 +945,61 @@ avm_status avm_run_endpoint_arrays(const avm_run* r, avm_endpoint_arrays* out) {
   return AVM_OK;
 }
 
+avm_status avm_run_set_signal(avm_run* r, double t0_ns, double dt_ns, int32_t n_bins) {
+  g_err.clear();
+  if (!r) return fail(AVM_E_ARG, "avm_run_set_signal: run is NULL");
+  if (r->opts.mode != AVM_MODE_BATCHED)
+    return fail(AVM_E_UNSUPPORTED, "avm_run_set_signal: the induced signal needs the batched mode");
+  if (r->executed && !r->synced) return fail(AVM_E_STATE, "avm_run_set_signal: the run is executing");
+  if (n_bins < 1) return fail(AVM_E_ARG, "avm_run_set_signal: n_bins < 1");
+  if (!(dt_ns > 0.0) || !std::isfinite(dt_ns) || !std::isfinite(t0_ns))
+    return fail(AVM_E_ARG, "avm_run_set_signal: need finite t0 and dt > 0");
+  DeviceGuard dg(r->gas->device);
+  if (dg.err != hipSuccess) return fail(AVM_E_HIP, "hipSetDevice: %s", hipGetErrorString(dg.err));
+  double* buf = nullptr;
+  const size_t n = (size_t)(r->n_aval ? r->n_aval : 1) * (size_t)n_bins;
+  hipError_t e = dmalloc(&buf, n);
+  if (e != hipSuccess) return fail(e == hipErrorOutOfMemory ? AVM_E_NOMEM : AVM_E_HIP, "avm_run_set_signal: %s", hipGetErrorString(e));
+  (void)hipFree(r->signal);
+  r->signal = buf;
+  SignalDev& Q = r->sigdev;
+  Q.out = buf;
+  Q.t0 = t0_ns;
+  Q.dt = dt_ns;
+  Q.n_bins = n_bins;
+  const FieldDev& F = r->field->dev;
+  if (F.kind == FIELD_SLAB) {
+    Q.w0 = F.z_lo;
+    Q.w1 = F.z_hi - F.z_lo;
+  } else {
+    Q.w0 = std::log(F.b);
+    Q.w1 = std::log(F.b / F.a);
+  }
+  e = batched_grid(r, r->opts.waves_per_cu, &r->grid, nullptr);
+  if (e != hipSuccess) return fail(AVM_E_HIP, "avm_run_set_signal: %s", hipGetErrorString(e));
+  if (r->graph_exec) {  // captured with the old kernel arguments
+    (void)hipGraphExecDestroy(r->graph_exec);
+    (void)hipGraphDestroy(r->graph);
+    r->graph_exec = nullptr;
+    r->graph = nullptr;
+  }
+  r->synced = 0;
+  r->executed = 0;
+  return AVM_OK;
+}
+
+avm_status avm_run_signal(const avm_run* r, uint32_t first, uint32_t n, double* out) {
+  if (!r || (!out && n)) return fail(AVM_E_ARG, "avm_run_signal: NULL argument");
+  if (!r->signal) return fail(AVM_E_STATE, "avm_run_signal: no signal requested (avm_run_set_signal)");
+  if (!r->synced) return fail(AVM_E_STATE, "avm_run_signal: call avm_run_sync first");
+  if ((uint64_t)first + n > r->n_aval) return fail(AVM_E_ARG, "avm_run_signal: avalanches beyond n_aval");
+  if (!n) return AVM_OK;
+  DeviceGuard dg(r->gas->device);
+  const size_t nb = (size_t)r->sigdev.n_bins;
+  HIP_TRY(hipMemcpy(out, r->signal + (size_t)first * nb, sizeof(double) * nb * n, hipMemcpyDeviceToHost));
+  return AVM_OK;
+}
+
 avm_status avm_run_timing(const avm_run* r, double* transport_ms, uint32_t* iterations) {
   if (!r) return fail(AVM_E_ARG, "avm_run_timing: run is NULL");
   if (!r->synced) return fail(AVM_E_STATE, "avm_run_timing: call avm_run_sync first");
@@ -891,3 +1025,214 @@ void avm_run_destroy(avm_run* r) {
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// autotuning
+// ---------------------------------------------------------------------------
+namespace {
+
+struct Fnv {
+  uint64_t h = 0xcbf29ce484222325ull;
+  void bytes(const void* p, size_t n) {
+    const unsigned char* c = static_cast<const unsigned char*>(p);
+    for (size_t i = 0; i < n; ++i) {
+      h ^= c[i];
+      h *= 0x100000001b3ull;
+    }
+  }
+  template <class T>
+  void val(const T& v) { bytes(&v, sizeof v); }
+};
+
+template <class T>
+hipError_t hash_device(Fnv& f, const T* p, size_t n) {
+  if (!p || !n) return hipSuccess;
+  std::vector<T> h(n);
+  const hipError_t e = hipMemcpy(h.data(), p, sizeof(T) * n, hipMemcpyDeviceToHost);
+  if (e == hipSuccess) f.bytes(h.data(), sizeof(T) * n);
+  return e;
+}
+
+// Key of a tuning problem: device, gas tables, field, primaries, options
+// that change the work (not the seed).
+hipError_t tune_key(const avm_gas* g, const avm_field* fl, const avm_primary* prim, int32_t on_dev,
+                    uint64_t n_prim, uint32_t n_aval, const avm_run_opts& o, uint32_t flags, uint64_t* key) {
+  Fnv f;
+  int dev = 0;
+  hipDeviceProp_t prop{};
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipGetDeviceProperties(&prop, dev);
+  if (e != hipSuccess) return e;
+  f.bytes(prop.gcnArchName, std::strlen(prop.gcnArchName));
+  f.val(prop.multiProcessorCount);
+  f.val(g->n_bins); f.val(g->n_ch); f.val(g->e_max); f.val(g->density);
+  e = hash_device(f, g->cum, ((size_t)g->n_bins + 1) * (size_t)g->n_ch);
+  if (e == hipSuccess) e = hash_device(f, g->ch, (size_t)g->n_ch);
+  const FieldDev& F = fl->dev;
+  f.val(F.kind); f.val(F.n_E); f.val(F.z_lo); f.val(F.z_hi); f.val(F.a); f.val(F.b);
+  f.val(F.n_r); f.val(F.n_phi); f.bytes(fl->B, sizeof fl->B);
+  if (e == hipSuccess) e = hash_device(f, F.E, (size_t)F.n_E * 3);
+  if (e == hipSuccess) e = hash_device(f, F.Er, (size_t)F.n_r * (size_t)F.n_phi);
+  if (e == hipSuccess) e = hash_device(f, F.Ephi, (size_t)F.n_r * (size_t)F.n_phi);
+  f.val(n_prim); f.val(n_aval);
+  if (e == hipSuccess && n_prim) {
+    if (on_dev)
+      e = hash_device(f, reinterpret_cast<const PrimaryRec*>(prim), n_prim);
+    else
+      f.bytes(prim, sizeof(avm_primary) * n_prim);
+  }
+  f.val(o.precision); f.val(o.majorant); f.val(o.mode); f.val(o.k_max); f.val(o.t_max_ns);
+  f.val(flags);
+  *key = f.h;
+  return e;
+}
+
+bool cache_lookup(const char* path, uint64_t key, int* fpp, int* wpc, int* bb, double* ms) {
+  if (!path) return false;
+  std::FILE* fp = std::fopen(path, "r");
+  if (!fp) return false;
+  char line[256];
+  bool found = false;
+  while (std::fgets(line, sizeof line, fp)) {
+    unsigned long long k = 0;
+    int a = 0, b = 0, c = 0;
+    double t = 0.0;
+    if (std::sscanf(line, "avm_tune 1 %llx %d %d %d %lf", &k, &a, &b, &c, &t) == 5 && k == key) {
+      *fpp = a; *wpc = b; *bb = c; *ms = t;
+      found = true;  // the last matching line wins
+    }
+  }
+  std::fclose(fp);
+  return found;
+}
+
+}  // namespace
+
+extern "C" avm_status avm_autotune(avm_gas* gas, const avm_field* field, const avm_primary* prim,
+                                   int32_t prim_on_device, uint64_t n_prim, uint32_t n_aval,
+                                   const avm_run_opts* base, uint32_t flags, const char* cache_path,
+                                   avm_tune_result* out) {
+  g_err.clear();
+  if (!gas || !field || !base || !out) return fail(AVM_E_ARG, "avm_autotune: NULL argument");
+  if (base->mode != AVM_MODE_BATCHED) return fail(AVM_E_ARG, "avm_autotune: only the batched mode has launch parameters");
+  if (flags & ~AVM_TUNE_BANDS) return fail(AVM_E_ARG, "avm_autotune: unknown flags 0x%x", flags);
+  std::memset(out, 0, sizeof *out);
+  avm_run_opts o = *base;
+  o.graph = 0;
+  if (o.flights_per_pass <= 0) o.flights_per_pass = 64;  // the run's default
+  const bool tune_bands = (flags & AVM_TUNE_BANDS) && o.majorant == AVM_MAJORANT_BANDED && !field->dev.has_b;
+  const int32_t bb0 = gas->band_bins;
+  DeviceGuard dg(gas->device);
+  if (dg.err != hipSuccess) return fail(AVM_E_HIP, "hipSetDevice: %s", hipGetErrorString(dg.err));
+  uint64_t key = 0;
+  HIP_TRY(tune_key(gas, field, prim, prim_on_device, n_prim, n_aval, o, flags, &key));
+  out->key = key;
+  {
+    int fpp = 0, wpc = 0, bb = 0;
+    double ms = 0.0;
+    if (cache_lookup(cache_path, key, &fpp, &wpc, &bb, &ms)) {
+      if (tune_bands && bb != gas->band_bins) {
+        const avm_status st = avm_gas_set_band_bins(gas, bb);
+        if (st != AVM_OK) return st;
+      }
+      out->flights_per_pass = fpp;
+      out->waves_per_cu = wpc;
+      out->band_bins = gas->band_bins;
+      out->from_cache = 1;
+      out->best_ms = ms;
+      out->start_ms = ms;
+      return AVM_OK;
+    }
+  }
+  avm_run* r = nullptr;
+  avm_status st = avm_run_create(gas, field, prim, prim_on_device, n_prim, n_aval, &o, &r);
+  if (st != AVM_OK) return st;
+  int max_blocks = 1;
+  {
+    int grid = 0;
+    const hipError_t e = batched_grid(r, 0, &grid, &max_blocks);
+    if (e != hipSuccess) {
+      avm_run_destroy(r);
+      return fail(AVM_E_HIP, "avm_autotune: %s", hipGetErrorString(e));
+    }
+  }
+  struct Trial { int fpp, wpc, bb; double ms; };
+  std::vector<Trial> done;
+  bool warm = false;
+  // best of two timed executions (after one warm-up execution of the run)
+  auto measure = [&](int fpp, int wpc, int bb, double* ms) -> avm_status {
+    if (fpp < 1) return fail(AVM_E_ARG, "avm_autotune: flights per pass %d < 1", fpp);
+    for (const Trial& t : done)
+      if (t.fpp == fpp && t.wpc == wpc && t.bb == bb) {
+        *ms = t.ms;
+        return AVM_OK;
+      }
+    if (bb != gas->band_bins) {
+      const avm_status s = avm_gas_set_band_bins(gas, bb);
+      if (s != AVM_OK) return s;
+    }
+    r->opts.flights_per_pass = fpp;
+    r->opts.waves_per_cu = wpc;
+    const hipError_t e = batched_grid(r, wpc, &r->grid, nullptr);
+    if (e != hipSuccess) return fail(AVM_E_HIP, "avm_autotune: %s", hipGetErrorString(e));
+    double best = INFINITY;
+    for (int rep = warm ? 0 : -1; rep < 2; ++rep) {
+      avm_status s = avm_run_execute(r);
+      if (s == AVM_OK) s = avm_run_sync(r);
+      if (s != AVM_OK) return s;
+      double t = 0.0;
+      s = avm_run_timing(r, &t, nullptr);
+      if (s != AVM_OK) return s;
+      if (rep >= 0 && t < best) best = t;
+    }
+    warm = true;
+    done.push_back({fpp, wpc, bb, best});
+    *ms = best;
+    return AVM_OK;
+  };
+  const int fpps[] = {8, 16, 32, 64, 128};
+  std::vector<int> bands = {bb0};
+  if (tune_bands)
+    for (int b : {25, 50, 100, 200, 400})
+      if (b < gas->n_bins && b != bb0) bands.push_back(b);
+  std::vector<int> wpcs = {0};
+  for (int j = 1; j < max_blocks; ++j) wpcs.push_back(j * (r->block / 64));
+  Trial best{o.flights_per_pass, o.waves_per_cu, bb0, INFINITY};
+  st = measure(best.fpp, best.wpc, best.bb, &best.ms);
+  if (st == AVM_OK) out->start_ms = best.ms;
+  auto consider = [&](int fpp, int wpc, int bb) {
+    if (st != AVM_OK) return;
+    double ms = 0.0;
+    st = measure(fpp, wpc, bb, &ms);
+    if (st == AVM_OK && ms < best.ms) best = {fpp, wpc, bb, ms};
+  };
+  // coordinate search: flights per pass, band width, flights per pass
+  // around the best again, resident waves
+  for (int f : fpps) consider(f, best.wpc, best.bb);
+  for (int b : bands) consider(best.fpp, best.wpc, b);
+  const int f0 = best.fpp;
+  for (int f : {f0 / 2, f0 * 2})
+    if (f >= 4 && f <= 256) consider(f, best.wpc, best.bb);
+  for (int w : wpcs) consider(best.fpp, w, best.bb);
+  avm_run_destroy(r);
+  if (st == AVM_OK && best.bb != gas->band_bins) st = avm_gas_set_band_bins(gas, best.bb);
+  if (st != AVM_OK) {
+    const std::string msg = g_err;
+    if (gas->band_bins != bb0) (void)avm_gas_set_band_bins(gas, bb0);
+    g_err = msg;
+    return st;
+  }
+  out->flights_per_pass = best.fpp;
+  out->waves_per_cu = best.wpc;
+  out->band_bins = best.bb;
+  out->trials = (int32_t)done.size();
+  out->best_ms = best.ms;
+  if (cache_path) {
+    std::FILE* fp = std::fopen(cache_path, "a");
+    if (!fp) return fail(AVM_E_ARG, "avm_autotune: cannot append to %s", cache_path);
+    std::fprintf(fp, "avm_tune 1 %016llx %d %d %d %.6f\n", (unsigned long long)key, best.fpp, best.wpc,
+                 best.bb, best.ms);
+    std::fclose(fp);
+  }
+  return AVM_OK;
+}

@@ -88,8 +88,6 @@ struct GasDev {
   double band_scale;        // n_bins / (E_max * band_bins): first guess of the band
   float gamma_f, inv_gamma_f, scale_f, band_scale_f;
   int32_t n_bins, n_ch, n_bands, band_bins;
-  ChanDev ch0;              // channel 0 by value (kernel argument: scalar registers)
-  ChanP<float> ch0_f;
 };
 
 // Where the hot tables are read from: `tot` and `cum0` hold nodes
@@ -104,6 +102,7 @@ struct TabView {
   const R* bgam;
   const R* binv;
   const R* bedge;
+  const ChanP<R>* ch;  // channel parameters
 };
 
 enum FieldKind : int32_t { FIELD_SLAB = 0, FIELD_POLAR = 1 };
@@ -137,12 +136,48 @@ struct RunParams {
   uint64_t budget_ticks;    // wall_clock64() ticks a transport kernel may run
 };
 
+// Induced signal on the readout electrode (Shockley-Ramo): bin j of
+// avalanche a, out[a n_bins + j], accumulates the change of the weighting
+// potential phi_w of the avalanche's electrons while they move during
+// [T_j, T_j+1), T_j = t0 + j dt (the change of induced charge in units of
+// the elementary charge, electrons carrying -1).  Readout electrode: the
+// z_hi plane of a slab, phi_w = (z - z_lo) / (z_hi - z_lo); the wire of the
+// coaxial geometry, phi_w = ln(b/rho) / ln(b/a).
+struct SignalDev {
+  double* out;
+  double t0, dt;
+  double w0, w1;   // slab: phi_w = (z - w0) / w1; coaxial wire: (w0 - ln rho) / w1
+  int32_t n_bins;
+  int32_t _pad;
+};
+
 // ---------------------------------------------------------------------------
 // Philox4x32-10 and uniform maps
 // ---------------------------------------------------------------------------
 struct Block { uint32_t w0, w1, w2, w3; };
 
+// Marks a wave-uniform value as redefined here (it stays in a scalar
+// register).  Work derived from it cannot be hoisted out of the enclosing
+// loop, where the derived values would stay live across the whole loop and
+// be spilled to VGPR lanes; recomputing them costs a few scalar adds.
+AVM_FN uint32_t pin_uniform(uint32_t v) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  asm volatile("" : "+s"(v));
+#endif
+  return v;
+}
+
+// The object p points to, through an address the compiler cannot see
+// through: loads of its fields stay where they are used instead of being
+// hoisted out of loops (for rarely used parameter blocks).
+template <class T>
+AVM_FN const T& pinned(const T* p) {
+  return *(p + pin_uniform(0u));
+}
+
 AVM_FN Block philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1) {
+  k0 = pin_uniform(k0);  // the round keys are formed here, not kept live
+  k1 = pin_uniform(k1);
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
     const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
@@ -373,6 +408,10 @@ struct Elec {
   int32_t band;
   uint32_t n_real, n_ion, n_null, n_masked, n_band, n_over;
   R Ex, Ey, Ez;  // slab: the avalanche's field, loaded once per electron
+  // induced signal: weighting potential where the current bin piece began,
+  // time and index of the next bin edge
+  double sphi, snext;
+  int32_t sj;
 };
 
 template <class R>
@@ -392,7 +431,6 @@ template <> struct Sel<double> {
   AVM_FN static double band_scale(const GasDev& G) { return G.band_scale; }
   AVM_FN static double gamma(const GasDev& G) { return G.gamma; }
   AVM_FN static double inv_gamma(const GasDev& G) { return G.inv_gamma; }
-  AVM_FN static const ChanP<double>& ch0(const GasDev& G) { return G.ch0; }
   AVM_FN static const ChanP<double>* ch(const GasDev& G) { return G.ch; }
   AVM_FN static const double* total(const GasDev& G) { return G.total; }
   AVM_FN static const double* cum0(const GasDev& G) { return G.cum0; }
@@ -406,7 +444,6 @@ template <> struct Sel<float> {
   AVM_FN static float band_scale(const GasDev& G) { return G.band_scale_f; }
   AVM_FN static float gamma(const GasDev& G) { return G.gamma_f; }
   AVM_FN static float inv_gamma(const GasDev& G) { return G.inv_gamma_f; }
-  AVM_FN static const ChanP<float>& ch0(const GasDev& G) { return G.ch0_f; }
   AVM_FN static const ChanP<float>* ch(const GasDev& G) { return G.ch_f; }
   AVM_FN static const float* total(const GasDev& G) { return G.total_f; }
   AVM_FN static const float* cum0(const GasDev& G) { return G.cum0_f; }
@@ -419,11 +456,11 @@ template <> struct Sel<float> {
 // The global-memory tables of precision R (no LDS copies).
 template <class R> AVM_FN TabView<R> global_view(const GasDev& G);
 template <> AVM_FN TabView<double> global_view<double>(const GasDev& G) {
-  return TabView<double>{G.total, G.cum0, G.n_bins + 1, G.band_gamma, G.band_inv, G.band_edge};
+  return TabView<double>{G.total, G.cum0, G.n_bins + 1, G.band_gamma, G.band_inv, G.band_edge, G.ch};
 }
 template <> AVM_FN TabView<float> global_view<float>(const GasDev& G) {
   return TabView<float>{G.total_f, G.cum0_f, G.n_bins + 1, G.band_gamma_f, G.band_inv_f,
-                        G.band_edge_f};
+                        G.band_edge_f, G.ch_f};
 }
 
 template <class R>
@@ -449,12 +486,13 @@ AVM_FN uint32_t region_status(const FieldDev& F, const Elec<R>& e) {
 }
 
 // Free flight of duration s from (r, v) with the field frozen at E: the
-// displacement is formed in R and added to the FP64 position.
-template <class R>
+// displacement is formed in R and added to the FP64 position.  kMayHaveB =
+// false compiles the B = 0 case only (the banded majorant requires B = 0).
+template <class R, bool kMayHaveB = true>
 AVM_FN void propagate(const FieldDev& F, const Elec<R>& e, R ax, R ay, R az, R Ex, R Ey, R Ez, R s,
                       double& rx, double& ry, double& rz, R& ux, R& uy, R& uz) {
   using Mr = M<R>;
-  if (!F.has_b) {
+  if (!kMayHaveB || !F.has_b) {
     const R hs2 = R(0.5) * s * s;
     rx = e.x + (double)Mr::fma(ax, hs2, e.vx * s);
     ry = e.y + (double)Mr::fma(ay, hs2, e.vy * s);
@@ -495,6 +533,76 @@ AVM_FN void propagate(const FieldDev& F, const Elec<R>& e, R ax, R ay, R az, R E
   ux = vp * bx + wx + cs * u0x + sn * cx;
   uy = vp * by + wy + cs * u0y + sn * cy;
   uz = vp * bz + wz + cs * u0z + sn * cz;
+}
+
+// ---- induced signal ----
+// Weighting potential of the readout electrode at (x, y, z).
+template <int kField>
+AVM_FN double weighting(const SignalDev& Q, double x, double y, double z) {
+  if (kField == FIELD_SLAB) return (z - Q.w0) / Q.w1;
+  return (Q.w0 - 0.5 * log(x * x + y * y)) / Q.w1;
+}
+
+// Time of bin edge j (edges past the last bin are never reached).
+AVM_FN double signal_edge(const SignalDev& Q, int32_t j) {
+  return j <= Q.n_bins ? Q.t0 + (double)j * Q.dt : __builtin_inf();
+}
+
+// Adds dq to bin j of avalanche `aval`; bins outside [0, n_bins) are dropped.
+AVM_FN void signal_deposit(const SignalDev& Q, uint32_t aval, int32_t j, double dq) {
+  if (j >= 0 && j < Q.n_bins) {
+#ifdef AVM_HOST_DEBUG
+    Q.out[(size_t)aval * (size_t)Q.n_bins + (size_t)j] += dq;
+#else
+    unsafeAtomicAdd(Q.out + (size_t)aval * (size_t)Q.n_bins + (size_t)j, dq);
+#endif
+  }
+}
+
+// Signal state of an electron at its birth (current position and time): the
+// weighting potential there and the first bin edge strictly after it.
+template <class R, int kField>
+AVM_FN void signal_birth(const SignalDev& Q, Elec<R>& e) {
+  e.sphi = weighting<kField>(Q, e.x, e.y, e.z);
+  int32_t j;
+  if (e.t < Q.t0) {
+    j = 0;
+  } else if (!(e.t < signal_edge(Q, Q.n_bins))) {
+    j = Q.n_bins + 1;
+  } else {
+    j = (int32_t)floor((e.t - Q.t0) / Q.dt) + 1;
+    j = j < 1 ? 1 : (j > Q.n_bins ? Q.n_bins : j);
+    while (!(signal_edge(Q, j) > e.t)) ++j;
+    while (j > 0 && signal_edge(Q, j - 1) > e.t) --j;
+  }
+  e.sj = j;
+  e.snext = signal_edge(Q, j);
+}
+
+// Bin edges passed during the flight that starts from state e and ends at
+// t_e: at each, the position from the flight formula closes the current
+// piece (its potential change goes to the bin the edge ends).  The pieces
+// between edges are closed lazily: consecutive flights chain, so the change
+// over a run of flights is the difference of its end points.
+template <class R, bool kMayHaveB, int kField>
+AVM_FN void signal_flight(const SignalDev& Q, const FieldDev& F, Elec<R>& e, R ax, R ay, R az, R Ex,
+                          R Ey, R Ez, double t_e) {
+  while (e.snext <= t_e) {
+    double mx, my, mz;
+    R wx, wy, wz;
+    propagate<R, kMayHaveB>(F, e, ax, ay, az, Ex, Ey, Ez, (R)(e.snext - e.t), mx, my, mz, wx, wy, wz);
+    const double phi = weighting<kField>(Q, mx, my, mz);
+    signal_deposit(Q, e.aval, e.sj - 1, phi - e.sphi);
+    e.sphi = phi;
+    e.sj += 1;
+    e.snext = signal_edge(Q, e.sj);
+  }
+}
+
+// At termination: the last piece, up to the end point.
+template <class R, int kField>
+AVM_FN void signal_end(const SignalDev& Q, const Elec<R>& e) {
+  signal_deposit(Q, e.aval, e.sj - 1, weighting<kField>(Q, e.x, e.y, e.z) - e.sphi);
 }
 
 // Smallest s >= 0 at which |v + a s|^2 reaches 2 k_a edge (energy at the band edge).
@@ -592,8 +700,8 @@ AVM_FN int decide(const GasDev& G, const TabView<R>& T, R en, R r_sel, R& margin
     c = lo;
   }
   margin = mg / r_sel;
-  const double e_lo = c == 0 ? G.ch0.e_lo : G.ch[c].e_lo;
-  const double e_hi = c == 0 ? G.ch0.e_hi : G.ch[c].e_hi;
+  const double e_lo = T.ch[c].e_lo;
+  const double e_hi = T.ch[c].e_hi;
   const double ed = (double)en;
   if (sizeof(R) == 4) {
     const double dl = fabs(ed - e_lo), dh = fabs(ed - e_hi);
@@ -609,9 +717,10 @@ AVM_FN int decide(const GasDev& G, const TabView<R>& T, R en, R r_sel, R& margin
 // energy in `child`) when the collision is an ionisation -- the caller then
 // finishes it with complete_ionisation() before the next pass -- otherwise
 // STEP_CONTINUE.
-template <class R, bool kBanded, int kField>
+template <class R, bool kBanded, int kField, bool kSignal = false>
 AVM_FN int32_t flight_step(Elec<R>& e, const GasDev& G, const TabView<R>& T, const FieldDev& F,
-                           const RunParams& P, Child<R>& child, uint32_t& status) {
+                           const RunParams& P, Child<R>& child, uint32_t& status,
+                           const SignalDev* Q = nullptr) {
   using Mr = M<R>;
   constexpr bool kMixed = sizeof(R) == 4;
   // position valid?
@@ -663,10 +772,10 @@ AVM_FN int32_t flight_step(Elec<R>& e, const GasDev& G, const TabView<R>& T, con
   uint32_t side = 0;
   if (kField == FIELD_SLAB) {
     side = slab_exit(e.z, (double)e.vz, (double)az, F.z_lo, F.z_hi, (double)tau_end, s_exit);
-    propagate<R>(F, e, ax, ay, az, Ex, Ey, Ez, side ? (R)s_exit : tau_end, rx, ry, rz, ux, uy, uz);
+    propagate<R, !kBanded>(F, e, ax, ay, az, Ex, Ey, Ez, side ? (R)s_exit : tau_end, rx, ry, rz, ux, uy, uz);
     if (side) rz = side == ST_HIGH ? F.z_hi : F.z_lo;
   } else {
-    propagate<R>(F, e, ax, ay, az, Ex, Ey, Ez, tau_end, rx, ry, rz, ux, uy, uz);
+    propagate<R, !kBanded>(F, e, ax, ay, az, Ex, Ey, Ez, tau_end, rx, ry, rz, ux, uy, uz);
     const double r2 = rx * rx + ry * ry;
     if (r2 <= F.a2 || r2 >= F.b2) {
       // bisection on the inside/outside predicate (excursions that leave
@@ -676,7 +785,7 @@ AVM_FN int32_t flight_step(Elec<R>& e, const GasDev& G, const TabView<R>& T, con
         const double mid = 0.5 * (lo + hi);
         double mx, my, mz;
         R wx_, wy_, wz_;
-        propagate<R>(F, e, ax, ay, az, Ex, Ey, Ez, (R)mid, mx, my, mz, wx_, wy_, wz_);
+        propagate<R, !kBanded>(F, e, ax, ay, az, Ex, Ey, Ez, (R)mid, mx, my, mz, wx_, wy_, wz_);
         const double m2 = mx * mx + my * my;
         if (m2 <= F.a2 || m2 >= F.b2)
           hi = mid;
@@ -684,7 +793,7 @@ AVM_FN int32_t flight_step(Elec<R>& e, const GasDev& G, const TabView<R>& T, con
           lo = mid;
       }
       s_exit = hi;
-      propagate<R>(F, e, ax, ay, az, Ex, Ey, Ez, (R)s_exit, rx, ry, rz, ux, uy, uz);
+      propagate<R, !kBanded>(F, e, ax, ay, az, Ex, Ey, Ez, (R)s_exit, rx, ry, rz, ux, uy, uz);
       const double q2 = rx * rx + ry * ry;
       side = q2 <= F.a2 ? ST_WIRE : ST_TUBE;
       const double sc = (side == ST_WIRE ? F.a : F.b) / sqrt(q2);
@@ -692,6 +801,8 @@ AVM_FN int32_t flight_step(Elec<R>& e, const GasDev& G, const TabView<R>& T, con
       ry = ry * sc;
     }
   }
+  if (kSignal) signal_flight<R, !kBanded, kField>(*Q, F, e, ax, ay, az, Ex, Ey, Ez,
+                                                   e.t + (side ? s_exit : (double)tau_end));
   e.x = rx; e.y = ry; e.z = rz;
   e.vx = ux; e.vy = uy; e.vz = uz;
   if (side) {
@@ -739,7 +850,7 @@ AVM_FN int32_t flight_step(Elec<R>& e, const GasDev& G, const TabView<R>& T, con
     return STEP_CONTINUE;
   }
   e.n_real += 1;
-  const int32_t kind = c == 0 ? G.ch0.kind : G.ch[c].kind;
+  const int32_t kind = T.ch[c].kind;
   if (kind == CH_ATTACHMENT) {
     status = ST_ATTACHED;
     return STEP_DONE;
@@ -753,7 +864,7 @@ AVM_FN int32_t flight_step(Elec<R>& e, const GasDev& G, const TabView<R>& T, con
   const Block w1 = draw(P, e.aval, e.eid, e.k, 1);
   const R uA = Mr::uni(w1.w0, w1.w1);
   const R uB = Mr::uni(w1.w2, w1.w3);
-  const ChanP<R>& ch = c == 0 ? Sel<R>::ch0(G) : Sel<R>::ch(G)[c];
+  const ChanP<R>& ch = T.ch[c];
   R e_new, cos_t;
   if (kind == CH_ELASTIC) {
     const R cchi = ch.angular ? R(1) - R(2) * uA / Mr::fma(R(1) - uA, en * ch.inv_screen8, R(1))
@@ -777,7 +888,7 @@ AVM_FN void complete_ionisation(Elec<R>& e, const GasDev& G, const TabView<R>& T
                                 const RunParams& P, Child<R>& child) {
   using Mr = M<R>;
   const int c = child.pc;
-  const ChanP<R>& ch = c == 0 ? Sel<R>::ch0(G) : Sel<R>::ch(G)[c];
+  const ChanP<R>& ch = T.ch[c];
   const R avail = child.pen - ch.loss;
   const Block w1 = draw(P, e.aval, e.eid, e.k, 1);
   const Block w2 = draw(P, e.aval, e.eid, e.k, 2);

@@ -66,13 +66,16 @@ hipError_t launch_load_primaries(const PrimaryRec* prim, uint64_t n, const Store
 hipError_t launch_reset(Counters* ctr, uint64_t n_prim, AvalStats* stats, uint32_t n_aval,
                         Totals* tot, hipStream_t st);
 hipError_t launch_generation(int fp32, int banded, int field_kind, const GasDev& G,
-                             const FieldDev& F, const RunParams& P, const Store& S,
+                             const FieldDev& F, const RunParams& P, const Store* S,
                              const uint32_t* active, uint32_t n_active, uint32_t* next,
                              Counters* ctr, hipStream_t st);
 hipError_t launch_persistent(int fp32, int banded, int field_kind, const GasDev& G,
-                             const FieldDev& F, const RunParams& P, const Store& S, Counters* ctr,
-                             int flights_per_pass, int grid, int block, hipStream_t st);
-hipError_t persistent_occupancy(int fp32, int banded, int field_kind, int block,
+                             const FieldDev& F, const RunParams& P, const Store* S, Counters* ctr,
+                             int flights_per_pass, const SignalDev* signal, int grid, int block,
+                             hipStream_t st);
+hipError_t launch_zero(double* p, size_t n, hipStream_t st);
+int persistent_block();  // threads per block of the persistent kernel
+hipError_t persistent_occupancy(int fp32, int banded, int field_kind, int signal, int block,
                                 int* blocks_per_cu);
 hipError_t launch_tables_f32(const double* cum, const double* total, const double* cum0,
                              size_t n_cum, int n_nodes, const double* bg, const double* be,

@@ -9,9 +9,16 @@ namespace avm {
 namespace {
 
 constexpr int kBlock = 256;        // set-up, plain and statistics kernels
-constexpr int kPBlock = 512;       // persistent kernel: one block of 8 waves per CU
-constexpr int kLdsBytes = 32768;   // bytes of each table slice staged in LDS
-constexpr int kLdsBands = 1024;    // band tables staged in LDS up to this size
+// Persistent kernel: one block per CU of AVM_PBLOCK threads (16 waves, 4 per
+// SIMD: the register budget is then 128 VGPRs), sharing one LDS copy of
+// the hot tables.
+#ifndef AVM_PBLOCK
+#define AVM_PBLOCK 1024
+#endif
+constexpr int kPBlock = AVM_PBLOCK;
+constexpr int kLdsBytes = 24576;   // bytes of each table slice staged in LDS
+constexpr int kLdsBands = 512;     // band tables staged in LDS up to this size
+constexpr int kLdsChannels = 64;   // channel parameters staged in LDS up to this many
 
 // ---------------------------------------------------------------------------
 // wave-level helpers (wave64)
@@ -229,13 +236,15 @@ AVM_FN void load_elec_tail(const GasDev& G, const TabView<R>& T, const FieldDev&
 // stack processing: inactive removed, new added), appended with one atomic
 // per wave.
 template <class R, bool kBanded, int kField>
-__global__ void __launch_bounds__(kBlock) k_generation(GasDev G, FieldDev F, RunParams P, Store S,
+__global__ void __launch_bounds__(kBlock) k_generation(GasDev G, FieldDev F, RunParams P,
+                                                       const Store* __restrict__ Sg,
                                                        const uint32_t* __restrict__ active,
                                                        uint32_t n_active, uint32_t* __restrict__ next,
                                                        Counters* ctr) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   const bool mine = i < n_active;
   const TabView<R> T = global_view<R>(G);
+  const Store& S = *Sg;
   bool ionised = false;
   uint32_t slot = 0;
   Elec<R> e;
@@ -334,7 +343,7 @@ struct Xfer {
 // Occupancy target of the persistent kernel (waves per SIMD); the register
 // budget follows from it.
 #ifndef AVM_PERSISTENT_WAVES_PER_EU
-#define AVM_PERSISTENT_WAVES_PER_EU 2
+#define AVM_PERSISTENT_WAVES_PER_EU (AVM_PBLOCK / 256)
 #endif
 
 // Every lane carries one electron at a time through up to `flights_per_pass`
@@ -352,10 +361,14 @@ struct Xfer {
 //      and picks up entries whose ready word shows the run's epoch.
 // A lane leaves when it is idle with no usable claim and live == 0: then no
 // electron exists anywhere and none can appear.
-template <class R, bool kBanded, int kField>
+//
+// kSignal: the electrons also deposit their induced signal (Shockley-Ramo,
+// binned in time) on the readout electrode.
+template <class R, bool kBanded, int kField, bool kSignal>
 __global__ void __launch_bounds__(kPBlock)
     __attribute__((amdgpu_waves_per_eu(AVM_PERSISTENT_WAVES_PER_EU, AVM_PERSISTENT_WAVES_PER_EU)))
-    k_persistent(GasDev G, FieldDev F, RunParams P, Store S, Counters* ctr, int flights_per_pass) {
+    k_persistent(GasDev G, FieldDev F, RunParams P, const Store* __restrict__ Sg, Counters* ctr,
+                 int flights_per_pass, SignalDev Q) {
   const uint32_t epoch = (uint32_t)ctr->epoch;
   constexpr unsigned long long kNone = ~0ull;
   __shared__ Xfer xfer_all[kPBlock / 64];
@@ -364,6 +377,7 @@ __global__ void __launch_bounds__(kPBlock)
   constexpr int kLdsNodes = kLdsBytes / (int)sizeof(R);
   __shared__ R s_tot[kLdsNodes], s_cum0[kLdsNodes];
   __shared__ R s_bg[kLdsBands], s_bi[kLdsBands], s_be[kLdsBands];
+  __shared__ ChanP<R> s_ch[kLdsChannels];
   const TabView<R> Tg = global_view<R>(G);
   const int n_lo = G.n_bins + 1 < kLdsNodes ? G.n_bins + 1 : kLdsNodes;
   for (int k = threadIdx.x; k < n_lo; k += kPBlock) {
@@ -377,8 +391,10 @@ __global__ void __launch_bounds__(kPBlock)
       s_bi[b] = Tg.binv[b];
       s_be[b] = Tg.bedge[b];
     }
+  const bool ch_lds = G.n_ch <= kLdsChannels;
+  if (ch_lds && (int)threadIdx.x < G.n_ch) s_ch[threadIdx.x] = Tg.ch[threadIdx.x];
   __syncthreads();
-  TabView<R> T{s_tot, s_cum0, n_lo, Tg.bgam, Tg.binv, Tg.bedge};
+  TabView<R> T{s_tot, s_cum0, n_lo, Tg.bgam, Tg.binv, Tg.bedge, ch_lds ? s_ch : Tg.ch};
   if (bands_lds) {
     T.bgam = s_bg;
     T.binv = s_bi;
@@ -403,11 +419,12 @@ __global__ void __launch_bounds__(kPBlock)
     uint32_t ended = 0;
     for (int f = 0; f < flights_per_pass && has && !cp; ++f) {
       uint32_t status = 0;
-      const int32_t r = flight_step<R, kBanded, kField>(e, G, T, F, P, child, status);
+      const int32_t r = flight_step<R, kBanded, kField, kSignal>(e, G, T, F, P, child, status, &Q);
       if (r == STEP_IONISED) {
         cp = true;
       } else if (r == STEP_DONE) {
-        write_end<R>(S, slot, e, P, status);
+        if (kSignal) signal_end<R, kField>(Q, e);
+        write_end<R>(pinned(Sg), slot, e, P, status);
         has = false;
         ended = 1;
       }
@@ -418,6 +435,7 @@ __global__ void __launch_bounds__(kPBlock)
       cx = e.x; cy = e.y; cz = e.z; ct = e.t;
     }
     // ---- exchange (wave in lockstep from here)
+    const Store& S = pinned(Sg);
     // 1. storage slots for all secondaries of this pass (dropped beyond the
     //    capacity; the stored ones are the lowest-ranked, slots are handed
     //    out in lane order)
@@ -507,6 +525,7 @@ __global__ void __launch_bounds__(kPBlock)
     }
     if (take) {
       load_elec_tail<R, kBanded, kField>(G, T, F, P, e);
+      if (kSignal) signal_birth<R, kField>(Q, e);
       has = true;
     } else if (!has && !done && claim != kNone) {
       if (claim < S.capacity && ld_coh_int(&S.qready[claim]) == epoch) {
@@ -518,6 +537,7 @@ __global__ void __launch_bounds__(kPBlock)
         e.eid = ld_coh_int(&S.eid[slot]);
         e.aval = ld_coh_int(&S.aval[slot]);
         load_elec_tail<R, kBanded, kField>(G, T, F, P, e);
+        if (kSignal) signal_birth<R, kField>(Q, e);
         has = true;
         claim = kNone;
       }
@@ -609,7 +629,7 @@ hipError_t launch_load_primaries(const PrimaryRec* prim, uint64_t n, const Store
 }
 
 template <class R, bool B, int FK>
-static void gen_one(const GasDev& G, const FieldDev& F, const RunParams& P, const Store& S,
+static void gen_one(const GasDev& G, const FieldDev& F, const RunParams& P, const Store* S,
                     const uint32_t* active, uint32_t n_active, uint32_t* next, Counters* ctr,
                     hipStream_t st) {
   hipLaunchKernelGGL((k_generation<R, B, FK>), dim3((n_active + kBlock - 1) / kBlock), dim3(kBlock),
@@ -618,7 +638,7 @@ static void gen_one(const GasDev& G, const FieldDev& F, const RunParams& P, cons
 
 template <class R>
 static void gen_prec(int banded, int fk, const GasDev& G, const FieldDev& F, const RunParams& P,
-                     const Store& S, const uint32_t* active, uint32_t n_active, uint32_t* next,
+                     const Store* S, const uint32_t* active, uint32_t n_active, uint32_t* next,
                      Counters* ctr, hipStream_t st) {
   if (banded) {
     if (fk == FIELD_SLAB)
@@ -634,7 +654,7 @@ static void gen_prec(int banded, int fk, const GasDev& G, const FieldDev& F, con
 }
 
 hipError_t launch_generation(int fp32, int banded, int field_kind, const GasDev& G,
-                             const FieldDev& F, const RunParams& P, const Store& S,
+                             const FieldDev& F, const RunParams& P, const Store* S,
                              const uint32_t* active, uint32_t n_active, uint32_t* next,
                              Counters* ctr, hipStream_t st) {
   if (n_active == 0) return hipSuccess;
@@ -645,51 +665,52 @@ hipError_t launch_generation(int fp32, int banded, int field_kind, const GasDev&
   return hipGetLastError();
 }
 
-template <class R>
-static const void* pick_persistent_prec(int banded, int fk) {
+template <class R, bool SIG>
+static const void* pick_persistent_sig(int banded, int fk) {
   if (banded)
-    return fk == FIELD_SLAB ? reinterpret_cast<const void*>(&k_persistent<R, true, FIELD_SLAB>)
-                            : reinterpret_cast<const void*>(&k_persistent<R, true, FIELD_POLAR>);
-  return fk == FIELD_SLAB ? reinterpret_cast<const void*>(&k_persistent<R, false, FIELD_SLAB>)
-                          : reinterpret_cast<const void*>(&k_persistent<R, false, FIELD_POLAR>);
+    return fk == FIELD_SLAB ? reinterpret_cast<const void*>(&k_persistent<R, true, FIELD_SLAB, SIG>)
+                            : reinterpret_cast<const void*>(&k_persistent<R, true, FIELD_POLAR, SIG>);
+  return fk == FIELD_SLAB ? reinterpret_cast<const void*>(&k_persistent<R, false, FIELD_SLAB, SIG>)
+                          : reinterpret_cast<const void*>(&k_persistent<R, false, FIELD_POLAR, SIG>);
 }
 
-hipError_t persistent_occupancy(int fp32, int banded, int field_kind, int block,
+static const void* pick_persistent(int fp32, int banded, int fk, int signal) {
+  if (fp32)
+    return signal ? pick_persistent_sig<float, true>(banded, fk) : pick_persistent_sig<float, false>(banded, fk);
+  return signal ? pick_persistent_sig<double, true>(banded, fk) : pick_persistent_sig<double, false>(banded, fk);
+}
+
+int persistent_block() { return kPBlock; }
+
+hipError_t persistent_occupancy(int fp32, int banded, int field_kind, int signal, int block,
                                 int* blocks_per_cu) {
-  const void* fn = fp32 ? pick_persistent_prec<float>(banded, field_kind)
-                        : pick_persistent_prec<double>(banded, field_kind);
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, block, 0);
-}
-
-template <class R, bool B, int FK>
-static void pers_one(const GasDev& G, const FieldDev& F, const RunParams& P, const Store& S,
-                     Counters* ctr, int fpp, int grid, int block, hipStream_t st) {
-  hipLaunchKernelGGL((k_persistent<R, B, FK>), dim3(grid), dim3(block), 0, st, G, F, P, S, ctr, fpp);
-}
-
-template <class R>
-static void pers_prec(int banded, int fk, const GasDev& G, const FieldDev& F, const RunParams& P,
-                      const Store& S, Counters* ctr, int fpp, int grid, int block, hipStream_t st) {
-  if (banded) {
-    if (fk == FIELD_SLAB)
-      pers_one<R, true, FIELD_SLAB>(G, F, P, S, ctr, fpp, grid, block, st);
-    else
-      pers_one<R, true, FIELD_POLAR>(G, F, P, S, ctr, fpp, grid, block, st);
-  } else {
-    if (fk == FIELD_SLAB)
-      pers_one<R, false, FIELD_SLAB>(G, F, P, S, ctr, fpp, grid, block, st);
-    else
-      pers_one<R, false, FIELD_POLAR>(G, F, P, S, ctr, fpp, grid, block, st);
-  }
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      blocks_per_cu, pick_persistent(fp32, banded, field_kind, signal), block, 0);
 }
 
 hipError_t launch_persistent(int fp32, int banded, int field_kind, const GasDev& G,
-                             const FieldDev& F, const RunParams& P, const Store& S, Counters* ctr,
-                             int flights_per_pass, int grid, int block, hipStream_t st) {
-  if (fp32)
-    pers_prec<float>(banded, field_kind, G, F, P, S, ctr, flights_per_pass, grid, block, st);
-  else
-    pers_prec<double>(banded, field_kind, G, F, P, S, ctr, flights_per_pass, grid, block, st);
+                             const FieldDev& F, const RunParams& P, const Store* S, Counters* ctr,
+                             int flights_per_pass, const SignalDev* signal, int grid, int block,
+                             hipStream_t st) {
+  SignalDev Q{};
+  if (signal) Q = *signal;
+  const void* fn = pick_persistent(fp32, banded, field_kind, signal != nullptr);
+  void* args[] = {const_cast<GasDev*>(&G), const_cast<FieldDev*>(&F), const_cast<RunParams*>(&P),
+                  const_cast<Store**>(&S), &ctr, &flights_per_pass, &Q};
+  return hipLaunchKernel(fn, dim3(grid), dim3(block), args, 0, st);
+}
+
+// Zero fill (a kernel, so that it can be captured into a graph).
+__global__ void k_zero(double* __restrict__ p, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    p[i] = 0.0;
+}
+
+hipError_t launch_zero(double* p, size_t n, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  size_t blocks = (n + kBlock - 1) / kBlock;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_zero, dim3((unsigned)blocks), dim3(kBlock), 0, st, p, n);
   return hipGetLastError();
 }
 

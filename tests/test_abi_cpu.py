@@ -49,6 +49,7 @@ def test_abi_version_and_sizes(A):
     assert W.PRIMARY_DTYPE.itemsize == 72
     assert C.sizeof(A._Counts) == 8 * 18 + 8
     assert C.sizeof(A._Opts) == 72
+    assert C.sizeof(A._TuneResult) == 48
 
 
 def test_argument_errors_without_a_device(A):
@@ -92,6 +93,11 @@ def test_argument_errors_without_a_device(A):
     assert L.avm_run_execute(None) == A.AVM_E_ARG
     assert L.avm_run_sync(None) == A.AVM_E_ARG
     assert L.avm_gas_get_info(None, None) == A.AVM_E_ARG
+    assert L.avm_gas_set_band_bins(None, 10) == A.AVM_E_ARG
+    assert L.avm_run_set_signal(None, 0.0, 0.01, 10) == A.AVM_E_ARG
+    assert L.avm_run_signal(None, 0, 0, None) == A.AVM_E_ARG
+    res = A._TuneResult()
+    assert L.avm_autotune(None, None, None, 0, 0, 0, C.byref(o), 0, None, C.byref(res)) == A.AVM_E_ARG
     L.avm_gas_destroy(None)
     L.avm_field_destroy(None)
     L.avm_run_destroy(None)

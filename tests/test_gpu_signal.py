@@ -1,0 +1,132 @@
+"""Induced signal (Shockley-Ramo on the readout electrode, binned in time)
+through the C-ABI against the oracle's, bin by bin, on the same seeded
+inputs; the sum rule at the benchmark's full size; FP32-mixed against FP64;
+graph replays; argument errors.  Deposits are device atomics, so values
+agree up to the order of rounding: the bar is 1e-9 relative to the row's
+largest bin."""
+import numpy as np
+import pytest
+
+from oracle import compare as CMP
+from paper_2509_15377_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def A():
+    from paper_2509_15377_amd import avm
+    if avm.device_count() < 1:
+        pytest.fail("no HIP device visible: the GPU tests need an MI355X")
+    return avm
+
+
+def _close(got, ref, rtol=1e-9):
+    scale = np.maximum(np.abs(ref).max(axis=1, keepdims=True), 1e-12)
+    err = np.abs(got - ref) / scale
+    assert err.max() <= rtol, f"max relative bin error {err.max():.3e}"
+    return err.max()
+
+
+def test_signal_toy_against_oracle(A, oracle_mod):
+    wl = W.toy(40)
+    spec = (0.0, 0.01, 200)
+    ref_ep, ref_sig = oracle_mod.run(wl.gas, wl.field, wl.primaries, wl.seed, signal=spec + (40,))
+    ep, tot, _, sig = A.run(wl, capacity=400_000, signal=spec, timeout_s=60.0)
+    CMP.assert_parity(ep, ref_ep)
+    print("toy signal max rel", _close(sig, ref_sig))
+
+
+def test_signal_argon_banded_against_oracle(A, oracle_mod):
+    wl = W.argon(40, band_bins=100)
+    spec = (-0.01, 0.004, 150)
+    g = oracle_mod.Gas(wl.gas, band_bins=100)
+    ref_ep, ref_sig = oracle_mod.run(g, wl.field, wl.primaries, wl.seed, banded=True,
+                                     signal=spec + (40,))
+    ep, _, _, sig = A.run(wl, majorant=A.BANDED, capacity=4_000_000, signal=spec, timeout_s=60.0)
+    CMP.assert_parity(ep, ref_ep)
+    assert np.abs(sig[:, :2]).max() == 0.0  # before the release nothing moves
+    print("argon signal max rel", _close(sig, ref_sig))
+
+
+def test_signal_wire_with_b_against_oracle(A, oracle_mod):
+    wl = W.wire(4)
+    spec = (0.0, 0.05, 300)
+    ref_ep, ref_sig = oracle_mod.run(wl.gas, wl.field, wl.primaries, wl.seed, k_max=20000,
+                                     signal=spec + (4,))
+    ep, _, _, sig = A.run(wl, capacity=2_000_000, k_max=20000, signal=spec, timeout_s=60.0)
+    CMP.assert_parity(ep, ref_ep)
+    print("wire signal max rel", _close(sig, ref_sig, rtol=1e-8))
+
+
+def test_signal_full_size_sum_rule_and_sample(A, oracle_mod):
+    """The benchmark configuration (1000 avalanches, banded, FP64) with the
+    signal on: per avalanche the bins add up to the sum of (z1 - z0)/d over
+    its endpoints (a property at any size), and every 100th avalanche
+    matches the oracle's replay bin by bin."""
+    wl = W.argon(band_bins=100)
+    spec = (0.0, 0.005, 240)
+    ep, tot, per, sig = A.run(wl, majorant=A.BANDED, capacity=8_000_000, signal=spec,
+                              timeout_s=60.0)
+    assert ep["t1"].max() < spec[0] + spec[1] * spec[2]
+    d = wl.field.z_hi_cm - wl.field.z_lo_cm
+    expect = np.bincount(ep["aval"], weights=(ep["z1"] - ep["z0"]) / d, minlength=wl.n_aval)
+    assert np.allclose(sig.sum(axis=1), expect, rtol=1e-10, atol=1e-10)
+    idx = W.subset_primaries(wl.primaries, 100)
+    _, ref_sig = oracle_mod.run(oracle_mod.Gas(wl.gas, band_bins=100), wl.field, wl.primaries[idx],
+                                wl.seed, banded=True, ids=idx, signal=spec + (wl.n_aval,))
+    print("full-size sample max rel", _close(sig[idx], ref_sig[idx]))
+
+
+def test_signal_fp32_mixed_statistics(A):
+    wl = W.argon(band_bins=100)
+    spec = (0.0, 0.005, 240)
+    _, _, _, s64 = A.run(wl, majorant=A.BANDED, capacity=8_000_000, signal=spec, timeout_s=60.0)
+    _, _, _, s32 = A.run(wl, majorant=A.BANDED, capacity=8_000_000, signal=spec, timeout_s=60.0,
+                         precision=A.FP32_MIXED)
+    q64, q32 = s64.sum(axis=1), s32.sum(axis=1)
+    rel = abs(q32.mean() - q64.mean()) / q64.mean()
+    m64, m32 = s64.mean(axis=0), s32.mean(axis=0)
+    shape = np.abs(m32 - m64).max() / m64.max()
+    print(f"signal charge fp64 {q64.mean():.2f} fp32 {q32.mean():.2f} rel {rel:.2e}; shape {shape:.2e}")
+    assert rel < 0.01 and shape < 0.02
+
+
+def test_signal_graph_replays(A):
+    wl = W.argon(64, band_bins=100)
+    g = A.Gas(wl.gas)
+    f = A.Field(wl.field)
+    kw = dict(seed=wl.seed, majorant=A.BANDED, capacity=1_000_000, timeout_s=60.0)
+    eager = A.Run(g, f, wl.primaries, wl.n_aval, **kw)
+    eager.set_signal(0.0, 0.005, 200)
+    eager.execute(); eager.sync()
+    ref = eager.signal()
+    gr = A.Run(g, f, wl.primaries, wl.n_aval, graph=True, **kw)
+    gr.set_signal(0.0, 0.005, 200)
+    for rep in range(3):
+        gr.execute(); gr.sync()
+        _close(gr.signal(), ref, rtol=1e-12)
+        eager.execute(); eager.sync()
+    gr.close()
+    eager.close()
+
+
+def test_signal_errors(A):
+    wl = W.toy(4)
+    g = A.Gas(wl.gas)
+    f = A.Field(wl.field)
+    r = A.Run(g, f, wl.primaries, 4, seed=1, mode=A.PLAIN)
+    with pytest.raises(A.AvmError) as e:
+        r.set_signal(0.0, 0.01, 10)
+    assert e.value.status == A.AVM_E_UNSUPPORTED
+    r.close()
+    r = A.Run(g, f, wl.primaries, 4, seed=1)
+    for bad in ((0.0, 0.01, 0), (0.0, 0.0, 10), (float("nan"), 0.01, 10)):
+        with pytest.raises(A.AvmError) as e:
+            r.set_signal(*bad)
+        assert e.value.status == A.AVM_E_ARG
+    r.n_signal_bins = 1
+    with pytest.raises(A.AvmError) as e:
+        r.signal()
+    assert e.value.status == A.AVM_E_STATE
+    r.close()

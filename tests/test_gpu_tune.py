@@ -1,0 +1,102 @@
+"""Band rebuilding and the launch autotuner through the C-ABI."""
+import numpy as np
+import pytest
+
+from oracle import compare as CMP
+from paper_2509_15377_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def A():
+    from paper_2509_15377_amd import avm
+    if avm.device_count() < 1:
+        pytest.fail("no HIP device visible: the GPU tests need an MI355X")
+    return avm
+
+
+def _sorted(ep):
+    return ep[np.lexsort((ep["eid"], ep["aval"]))]
+
+
+def test_set_band_bins_rebuilds_the_oracle_bands(A, oracle_mod):
+    wl = W.argon(20)
+    g = A.Gas(wl.gas, band_bins=100)
+    f = A.Field(wl.field)
+    g.set_band_bins(50)
+    assert g.band_bins == 50 and g.n_bands == 400
+    _, bg, be = g.tables()
+    o = oracle_mod.Gas(wl.gas, band_bins=50)
+    for b in range(g.n_bands):
+        gb, eb = o.band(b)
+        assert bg[b] == pytest.approx(gb, rel=1e-15)
+        assert eb == be[b]
+    ref = oracle_mod.run(o, wl.field, wl.primaries, wl.seed, banded=True)
+    ep, _, _ = A.run(gas=g, field=f, primaries=wl.primaries, n_aval=20, seed=wl.seed,
+                     majorant=A.BANDED, capacity=2_000_000, timeout_s=60.0)
+    print("band width 50", CMP.assert_parity(ep, ref))
+
+
+def test_band_change_between_executes(A):
+    """A run created with bands, executed after the gas lost them, refuses
+    (AVM_E_STATE); a graph captured before a band change is captured again
+    and gives the eager result at the new width."""
+    wl = W.argon(32)
+    g = A.Gas(wl.gas, band_bins=100)
+    f = A.Field(wl.field)
+    kw = dict(seed=wl.seed, majorant=A.BANDED, capacity=2_000_000, timeout_s=60.0)
+    r = A.Run(g, f, wl.primaries, 32, **kw)
+    g.set_band_bins(0)
+    with pytest.raises(A.AvmError) as e:
+        r.execute()
+    assert e.value.status == A.AVM_E_STATE
+    g.set_band_bins(100)
+    gr = A.Run(g, f, wl.primaries, 32, graph=True, **kw)
+    gr.execute(); gr.sync()
+    at100 = _sorted(gr.endpoints())
+    g.set_band_bins(40)
+    gr.execute(); gr.sync()
+    at40 = _sorted(gr.endpoints())
+    r.execute(); r.sync()
+    eager40 = _sorted(r.endpoints())
+    assert at40.tobytes() == eager40.tobytes()
+    assert at100.tobytes() != at40.tobytes()
+    r.close()
+    gr.close()
+
+
+def test_autotune_choice_and_cache(A, oracle_mod, tmp_path):
+    wl = W.argon(200)
+    g = A.Gas(wl.gas, band_bins=100)
+    f = A.Field(wl.field)
+    cache = tmp_path / "tune.txt"
+    kw = dict(seed=wl.seed, majorant=A.BANDED, capacity=8_000_000, timeout_s=60.0)
+    res = A.autotune(g, f, wl.primaries, wl.n_aval, cache=str(cache), **kw)
+    print("autotune", res)
+    assert res["trials"] >= 8 and res["from_cache"] == 0
+    assert res["best_ms"] <= res["start_ms"]
+    assert g.band_bins == res["band_bins"]
+    assert cache.read_text().count("avm_tune 1") == 1
+    # launch parameters do not change results: tuned == default at that band width
+    tuned = A.Run(g, f, wl.primaries, wl.n_aval, flights_per_pass=res["flights_per_pass"],
+                  waves_per_cu=res["waves_per_cu"], **kw)
+    tuned.execute(); tuned.sync()
+    plain = A.Run(g, f, wl.primaries, wl.n_aval, **kw)
+    plain.execute(); plain.sync()
+    a, b = _sorted(tuned.endpoints()), _sorted(plain.endpoints())
+    assert a.tobytes() == b.tobytes()
+    tuned.close()
+    plain.close()
+    # the chosen band width against the oracle built with it
+    sub = wl.primaries[wl.primaries["aval"] < 10]
+    ref = oracle_mod.run(oracle_mod.Gas(wl.gas, band_bins=res["band_bins"]), wl.field, sub, wl.seed,
+                         banded=True)
+    print("tuned bands", CMP.assert_parity(a[a["aval"] < 10], ref))
+    # second call: from the cache, no trials, same choice, gas set to it
+    g2 = A.Gas(wl.gas, band_bins=100)
+    res2 = A.autotune(g2, f, wl.primaries, wl.n_aval, cache=str(cache), **kw)
+    assert res2["from_cache"] == 1 and res2["trials"] == 0 and res2["key"] == res["key"]
+    for k in ("flights_per_pass", "waves_per_cu", "band_bins"):
+        assert res2[k] == res[k]
+    assert g2.band_bins == res["band_bins"]

@@ -1,0 +1,127 @@
+"""The remaining benchmark workloads through the C-ABI: per-avalanche fields
+(8192 avalanches, E from 25 to 55 kV/cm), high gain with attachment
+(256 avalanches at 55 kV/cm), and the wire chamber with a polar field map
+and an axial magnetic field.  Per-trajectory parity with the FP64 oracle on
+avalanche subsets (which it replays exactly on its own), batched against
+plain scheduling, and FP32-mixed against FP64 statistics."""
+import numpy as np
+import pytest
+from scipy import stats
+
+from oracle import compare as CMP
+from paper_2509_15377_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def A():
+    from paper_2509_15377_amd import avm
+    if avm.device_count() < 1:
+        pytest.fail("no HIP device visible: the GPU tests need an MI355X")
+    return avm
+
+
+def _drift(ep):
+    m = ep["status"] == 2
+    return (ep["z1"][m] - ep["z0"][m]).sum() / (ep["t1"][m] - ep["t0"][m]).sum()
+
+
+@pytest.fixture(scope="module")
+def batched_fp64(A):
+    """The full 8192-avalanche run in the benchmark's launch configuration
+    (batched, banded, FP64); ~1e8 electrons, so only counts come back."""
+    wl = W.batched(band_bins=100)
+    g = A.Gas(wl.gas, band_bins=100)
+    f = A.Field(wl.field)
+    r = A.Run(g, f, wl.primaries, wl.n_aval, seed=wl.seed, majorant=A.BANDED,
+              capacity=400_000_000, timeout_s=100.0)
+    r.execute()
+    r.sync()
+    tot, per = r.counts(), r.avalanche_counts()
+    r.close()
+    return wl, g, f, tot, per
+
+
+def test_batched_fields_invariants(batched_fp64):
+    wl, _, _, tot, per = batched_fp64
+    assert tot["truncated"] == 0
+    assert tot["n_endpoints"] == wl.n_aval + tot["n_ion"]
+    assert np.array_equal(per["n_endpoints"], 1 + per["n_ion"])
+    assert per["n_endpoints"].sum() == tot["n_endpoints"]
+    # gain grows with the avalanche's own field
+    E = -wl.field.E_vcm[:, 2]
+    rho = stats.spearmanr(E, per["n_endpoints"]).statistic
+    print("8192 avalanches: electrons", tot["n_endpoints"], "spearman(E, gain)", rho)
+    assert rho > 0.5
+
+
+def test_batched_fields_sampled_counts(batched_fp64, oracle_mod):
+    """Every 512th avalanche of the full run (16 fields across the range):
+    its per-avalanche counts equal the oracle's replay of that avalanche."""
+    wl, _, _, _, per = batched_fp64
+    idx = W.subset_primaries(wl.primaries, 512)
+    ref = oracle_mod.run(oracle_mod.Gas(wl.gas, band_bins=100), wl.field, wl.primaries[idx],
+                         wl.seed, banded=True, ids=idx)
+    avals = wl.primaries["aval"][idx]
+    n_ep = np.bincount(ref["aval"], minlength=wl.n_aval)[avals]
+    n_real = np.bincount(ref["aval"], weights=ref["n_real"], minlength=wl.n_aval)[avals]
+    print("sampled gains", n_ep)
+    assert np.array_equal(per["n_endpoints"][avals], n_ep)
+    assert np.array_equal(per["n_real"][avals], n_real.astype(np.int64))
+
+
+def test_batched_fields_oracle_first16(A, oracle_mod):
+    """The first 16 avalanches (16 random fields) per trajectory against the
+    oracle."""
+    wl = W.batched(16, band_bins=100)
+    ref = oracle_mod.run(oracle_mod.Gas(wl.gas, band_bins=100), wl.field, wl.primaries,
+                         wl.seed, banded=True)
+    ep, _, _ = A.run(wl, majorant=A.BANDED, capacity=20_000_000, timeout_s=60.0)
+    rep = CMP.assert_parity(ep, ref)
+    print("per-avalanche fields, first 16", rep)
+
+
+def test_batched_fields_plain_equals_batched(A):
+    """Plain (generation-synchronous) and batched (persistent) scheduling give
+    the same bits on the first 128 avalanches of the per-avalanche-field
+    workload."""
+    wl = W.batched(128, band_bins=100)
+    kw = dict(majorant=A.BANDED, capacity=20_000_000, timeout_s=60.0)
+    a, ta, _ = A.run(wl, mode=A.PLAIN, **kw)
+    b, tb, _ = A.run(wl, mode=A.BATCHED, **kw)
+    assert a.tobytes() == b.tobytes()
+    assert ta == tb
+
+
+@pytest.fixture(scope="module")
+def highgain_pair(A):
+    wl = W.highgain(band_bins=100)
+    kw = dict(majorant=A.BANDED, capacity=60_000_000, timeout_s=100.0)
+    r64 = A.run(wl, precision=A.FP64, **kw)
+    r32 = A.run(wl, precision=A.FP32_MIXED, **kw)
+    return wl, r64, r32
+
+
+def test_highgain_fp32_statistics(highgain_pair):
+    wl, (e64, t64, p64), (e32, t32, p32) = highgain_pair
+    assert t64["truncated"] == 0 and t32["truncated"] == 0
+    assert t64["n_att"] > 0 and t32["n_att"] > 0
+    g64 = p64["n_endpoints"].astype(float)
+    g32 = p32["n_endpoints"].astype(float)
+    rel = abs(g32.mean() - g64.mean()) / g64.mean()
+    v64, v32 = _drift(e64), _drift(e32)
+    print(f"highgain mean gain fp64 {g64.mean():.1f} fp32 {g32.mean():.1f} rel {rel:.2e} "
+          f"corr {np.corrcoef(g64, g32)[0, 1]:.4f}; attached {t64['n_att']} {t32['n_att']}; "
+          f"drift rel {abs(v32 - v64) / v64:.2e}")
+    assert rel < 0.01
+    assert abs(v32 - v64) / v64 < 0.005
+    m64, m32 = e64["status"] == 2, e32["status"] == 2
+    for k in ("t1", "e1", "x1"):
+        assert stats.ks_2samp(e64[k][m64], e32[k][m32]).pvalue > 0.01, k
+    assert stats.ks_2samp(g64, g32).pvalue > 0.01
+    # effective gain excludes attached electrons
+    att64 = np.bincount(e64["aval"][e64["status"] == 3], minlength=wl.n_aval)
+    att32 = np.bincount(e32["aval"][e32["status"] == 3], minlength=wl.n_aval)
+    eff64, eff32 = (g64 - att64).mean(), (g32 - att32).mean()
+    assert abs(eff32 - eff64) / eff64 < 0.01
