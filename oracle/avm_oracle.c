@@ -501,6 +501,57 @@ void orc_propagate(const double r0[3], const double v0[3], const double E[3], co
   }
 }
 
+/* Bound of the energy along a helical flight (frozen E, B != 0), for the
+ * banded majorant.  Along B the speed is |v_par + a_par s| <= vp + ap s with
+ * vp = |v_par|, ap = |a_par|.  Across B the velocity is w + R(omega s) u0
+ * (w the E x B drift, u0 = v_perp - w turned by the angle omega s): it moves
+ * away from v_perp by |R u0 - u0| = 2 |u0| sin(omega s / 2) <= |u0| omega s,
+ * and its length never exceeds |w| + |u0|.  So, with p = |v_perp|,
+ * q = |u0| omega and m = |w| + |u0| (>= p),
+ *   2 k_a e(s) <= (vp + ap s)^2 + min(p + q s, m)^2,
+ * which is exact at s = 0 and grows with s. */
+void orc_helical_bound(const double v[3], const double E[3], const double B[3], double out[5])
+{
+  const double k_a = orc_k_a(), k_b = orc_k_b();
+  double bb = dot3(B, B);
+  double bmag = sqrt(bb);
+  double bh[3] = {B[0] / bmag, B[1] / bmag, B[2] / bmag};
+  double acc[3] = {-k_a * E[0], -k_a * E[1], -k_a * E[2]};
+  double vpar = dot3(v, bh), apar = dot3(acc, bh);
+  double exb[3];
+  cross3(E, B, exb);
+  double wd[3], u0[3], vperp[3];
+  for (int i = 0; i < 3; ++i) {
+    wd[i] = (k_a / k_b) * exb[i] / bb;
+    vperp[i] = v[i] - vpar * bh[i];
+    u0[i] = vperp[i] - wd[i];
+  }
+  double un = sqrt(dot3(u0, u0));
+  out[0] = fabs(vpar);
+  out[1] = fabs(apar);
+  out[2] = sqrt(dot3(vperp, vperp));
+  out[3] = un * (k_b * bmag);
+  out[4] = sqrt(dot3(wd, wd)) + un;
+}
+
+/* Smallest s >= 0 at which the helical energy bound (b = the five numbers
+ * above) reaches e_edge: 0 if it is there already, +inf if never. */
+double orc_helical_bound_root(const double b[5], double e_edge)
+{
+  const double vp = b[0], ap = b[1], p = b[2], q = b[3], m = b[4];
+  const double T = 2.0 * orc_k_a() * e_edge;
+  const double c = T - (vp * vp + p * p);
+  if (!(c > 0.0)) return 0.0;
+  /* unsaturated branch: (ap^2 + q^2) s^2 + 2 (vp ap + p q) s - c = 0 */
+  const double A = ap * ap + q * q, Bq = 2.0 * (vp * ap + p * q);
+  if (A == 0.0 && Bq == 0.0) return INFINITY;
+  const double s1 = 2.0 * c / (Bq + sqrt(Bq * Bq + 4.0 * A * c));
+  if (q == 0.0 || p + q * s1 <= m) return s1;
+  /* saturated: (vp + ap s)^2 + m^2 = T, reached after p + q s = m */
+  if (ap == 0.0 || !(T > m * m)) return INFINITY;
+  return (sqrt(T - m * m) - vp) / ap;
+}
+
 /* Real roots of A s^2 + B s + C = 0, ascending; the numerically stable form
  * q = -(B + sgn(B) sqrt(disc))/2, roots q/A and C/q. */
 static int quad_roots(double A, double B, double C, double out[2])
@@ -740,6 +791,12 @@ static void signal_flight(const ctx_t* cx, uint32_t aval, const double r_s[3], c
 
 static double energy_of(const double v[3]) { return dot3(v, v) / (2.0 * orc_k_a()); }
 
+/* Decisions that saw an interpolated total rate above the majorant in use
+ * (a majorant that is not one; counted for the pins, never expected). */
+static uint64_t g_majorant_violations = 0;
+uint64_t orc_majorant_violations(void) { return __atomic_load_n(&g_majorant_violations, __ATOMIC_RELAXED); }
+void orc_reset_majorant_violations(void) { __atomic_store_n(&g_majorant_violations, 0, __ATOMIC_RELAXED); }
+
 /* Set v to speed sqrt(2 k_a e) along unit vector d. */
 static void set_velocity(double v[3], double e, const double d[3])
 {
@@ -774,6 +831,7 @@ static int transport(const ctx_t* cx, elec e, estack* st, orc_endpoint* ep)
   const orc_opts* o = cx->o;
   const double k_a = orc_k_a();
   const int banded = o->banded && g->n_bands > 1;
+  const int helical = banded && dot3(f->B, f->B) != 0.0;
   memset(ep, 0, sizeof(*ep));
   ep->x0 = e.r0[0];
   ep->y0 = e.r0[1];
@@ -804,13 +862,28 @@ static int transport(const ctx_t* cx, elec e, estack* st, orc_endpoint* ep)
     double u2 = orc_u53(w[2], w[3]);
     double E[3];
     orc_field_eval(f, e.r, e.aval, E);
+    /* with B the band must bound the energy over the whole flight: raise it
+     * until the helical bound at the flight start lies below its edge */
+    double hb[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    if (helical) {
+      orc_helical_bound(e.v, E, f->B, hb);
+      while (band < g->n_bands - 1 && (hb[0] * hb[0] + hb[2] * hb[2]) / (2.0 * k_a) >= g->band_edge[band])
+        band++;
+    }
     double gam = banded ? g->band_gamma[band] : g->gamma;
     double tau = -log(u1) / gam;
     /* the flight ends at the earliest of: the collision candidate, the band
      * edge (banded majorant), the time limit */
     double tau_end = tau;
     int cut = 0; /* 1 band edge, 2 time limit */
-    if (banded && band < g->n_bands - 1) {
+    if (helical && band < g->n_bands - 1) {
+      /* cut where the energy bound reaches the edge: Gamma_b holds before */
+      double tc = orc_helical_bound_root(hb, g->band_edge[band]);
+      if (tc < tau_end) {
+        tau_end = tc;
+        cut = 1;
+      }
+    } else if (banded && band < g->n_bands - 1) {
       double rr[3], vv[3];
       orc_propagate(e.r, e.v, E, f->B, tau, rr, vv);
       if (energy_of(vv) >= g->band_edge[band]) {
@@ -901,6 +974,7 @@ static int transport(const ctx_t* cx, elec e, estack* st, orc_endpoint* ep)
     int over = lookup(g, en, &kb, &fb);
     if (over) ep->n_overflow++;
     double nu_tot = total_at(g, kb, fb, over);
+    if (nu_tot > gam) __atomic_fetch_add(&g_majorant_violations, 1, __ATOMIC_RELAXED);
     double r_sel = u2 * gam;
     if (r_sel >= nu_tot) {
       ep->n_null++;
@@ -1089,8 +1163,6 @@ int orc_run_signal(const orc_gas* g, const orc_field* f, const orc_primary* prim
       if (prim[i].aval >= sig->n_rows) return ORC_E_ARG;
   }
   if (o->k_max > (1u << 30) - 1u) return ORC_E_ARG;
-  if (o->banded && f->B[0] * f->B[0] + f->B[1] * f->B[1] + f->B[2] * f->B[2] != 0.0)
-    return ORC_E_ARG; /* the band bound needs a convex energy along the flight */
   if (f->kind == FIELD_SLAB && f->n_E > 1)
     for (uint64_t i = 0; i < n_prim; ++i)
       if (prim[i].aval >= f->n_E) return ORC_E_ARG;

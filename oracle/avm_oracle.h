@@ -100,7 +100,7 @@ typedef struct {
 
 typedef struct {
   uint64_t seed;
-  int32_t banded;      /* 0: global majorant; 1: banded majorant (B = 0 only) */
+  int32_t banded;      /* 0: global majorant; 1: banded majorant (with B: helical bound) */
   int32_t fifo;        /* 0: LIFO stack per avalanche; 1: FIFO queue */
   double t_max_ns;     /* +inf: no time limit */
   uint32_t k_max;      /* flight index limit (<= 2^30-1) */
@@ -163,6 +163,15 @@ double orc_band_root(const double v[3], const double a[3], double e_edge);
 /* Free flight over time s in a field frozen at E, optional B. */
 void orc_propagate(const double r0[3], const double v0[3], const double E[3], const double B[3],
                    double s, double r[3], double v[3]);
+/* Helical-flight energy bound for the banded majorant with B:
+ * out = {vp, ap, p, q, m} with 2 k_a e(s) <= (vp + ap s)^2 + min(p + q s, m)^2. */
+void orc_helical_bound(const double v[3], const double E[3], const double B[3], double out[5]);
+/* Smallest s >= 0 at which that bound reaches e_edge (0: already; +inf: never). */
+double orc_helical_bound_root(const double b[5], double e_edge);
+/* Decisions (all runs of the process) that saw an interpolated total rate
+ * above the majorant in use; never expected to be non-zero. */
+uint64_t orc_majorant_violations(void);
+void orc_reset_majorant_violations(void);
 double orc_k_a(void);
 double orc_k_b(void);
 

@@ -111,6 +111,10 @@ def lib():
         L.orc_band_root.argtypes = [dp, dp, C.c_double]
         L.orc_band_root.restype = C.c_double
         L.orc_propagate.argtypes = [dp, dp, dp, dp, C.c_double, dp, dp]
+        L.orc_helical_bound.argtypes = [dp, dp, dp, dp]
+        L.orc_helical_bound_root.argtypes = [dp, C.c_double]
+        L.orc_helical_bound_root.restype = C.c_double
+        L.orc_majorant_violations.restype = C.c_uint64
         L.orc_k_a.restype = C.c_double
         L.orc_k_b.restype = C.c_double
         _lib = L
