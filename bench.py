@@ -28,6 +28,13 @@ OPS_PER_REAL = 220
 OPS_PER_ION = 280
 PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 
+# Oracle samples per workload (avalanche ids divisible by the modulus, which
+# replay exactly on their own): about 5-30 s on the host cores.  Electron
+# capacity per workload.
+CPU_MODULUS = {"toy": 1, "argon": 1, "batched": 64, "highgain": 16, "wire": 128}
+CAPACITY = {"toy": 2_000_000, "argon": 16_000_000, "batched": 200_000_000,
+            "highgain": 60_000_000, "wire": 90_000_000}
+
 # HBM traffic of the transport kernel from two counter passes (FETCH_SIZE,
 # WRITE_SIZE per dispatch), valid only for the kernel sources it was taken on.
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_persistent_argon1000_fp64_banded.json")
@@ -135,6 +142,8 @@ def main():
         return
     if args.headline_only:
         args.no_mixed = args.no_plain = args.no_cpu = True
+    if args.workload != "argon":
+        args.no_plain = True  # the generation loop on the global majorant: minutes
     import numpy as np
     import torch
 
@@ -148,7 +157,7 @@ def main():
     stream = torch.cuda.current_stream()
     gas = avm.Gas(wl.gas, 0)
     field = avm.Field(wl.field, 0)
-    capacity = 16_000_000
+    capacity = CAPACITY[args.workload]
 
     use_graph = not args.eager
 
@@ -200,7 +209,7 @@ def main():
             "ms_per_step": mms, "kernel_ms": sum(mk) / len(mk),
             "mean_gain": mc["n_endpoints"] / wl.n_aval, "graph": use_graph}
         mr.close()
-    if not args.headline_only:
+    if not args.headline_only and args.workload == "argon":
         side_legs(args, make, timed, paths, gas, field, wl, capacity, stream)
     if not args.no_plain:
         # the paper's scheduling (one kernel per transport iteration, host
@@ -226,20 +235,24 @@ def main():
         from oracle import oracle as O
         og = O.Gas(wl.gas, band_bins=band_bins)
         of = O.Field(wl.field)
+        mod = CPU_MODULUS[args.workload]
+        sel = W.subset_primaries(wl.primaries, mod)
         t2 = time.perf_counter()
-        ep, threads = O.run(og, of, wl.primaries, wl.seed, banded=True, return_threads=True)
+        ep, threads = O.run(og, of, wl.primaries[sel], wl.seed, banded=True, ids=sel,
+                            return_threads=True)
         tc = time.perf_counter() - t2
-        idx = W.subset_primaries(wl.primaries, 20)
+        idx = W.subset_primaries(wl.primaries, 20 * mod)
         t3 = time.perf_counter()
         ep1 = O.run(og, of, wl.primaries[idx], wl.seed, banded=True, ids=idx, threads=1)
         t1c = time.perf_counter() - t3
         cpu = {"value": float(ep["n_real"].sum() / tc), "unit": "real collisions/s",
                "cores": int(threads), "kind": "oracle",
-               "sample": f"all {wl.n_aval} avalanches, banded majorant, FP64, {tc:.1f} s "
-                         f"on {threads} threads",
+               "sample": (f"all {wl.n_aval} avalanches" if mod == 1 else
+                          f"avalanches with id % {mod} == 0 ({sel.size} of {wl.n_aval})")
+                         + f", banded majorant, FP64, {tc:.1f} s on {threads} threads",
                "secondaries_per_s": float(ep["n_ion"].sum() / tc),
                "single_thread": {"value": float(ep1["n_real"].sum() / t1c),
-                                 "sample": f"avalanches with id % 20 == 0 ({idx.size}), {t1c:.1f} s"}}
+                                 "sample": f"avalanches with id % {20 * mod} == 0 ({idx.size}), {t1c:.1f} s"}}
 
     line = {
         "metric": "electron real collisions/s (secondaries/s alongside) at gain ~1e3",
@@ -263,8 +276,9 @@ def main():
         "null_fraction": (c["n_null"] + c["n_masked"]) / max(flights, 1),
         "paths": paths,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_LANE_OPS,
-                     "unit": "lane-ops/s", "frac": achieved / PEAK_LANE_OPS, "traffic": measured_traffic(),
-                     "kernel": "k_persistent<banded,slab>", "kernel_ms": k_ms,
+                     "unit": "lane-ops/s", "frac": achieved / PEAK_LANE_OPS,
+                     "traffic": measured_traffic() if args.workload == "argon" else None,
+                     "kernel": "k_persistent<banded,%s>" % ("polar" if args.workload == "wire" else "slab"), "kernel_ms": k_ms,
                      "ops_per_launch": ops},
         "cpu_baseline": cpu,
     }

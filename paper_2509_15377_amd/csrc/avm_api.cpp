@@ -614,8 +614,8 @@ avm_status avm_run_create(const avm_gas* gas, const avm_field* field, const avm_
   if (o.majorant != AVM_MAJORANT_GLOBAL && o.majorant != AVM_MAJORANT_BANDED) return fail(AVM_E_ARG, "avm_run_create: bad majorant");
   if (o.majorant == AVM_MAJORANT_BANDED && gas->n_bands < 2)
     return fail(AVM_E_ARG, "avm_run_create: banded majorant needs a gas built with band_bins > 0");
-  if (o.majorant == AVM_MAJORANT_BANDED && field->dev.has_b)
-    return fail(AVM_E_UNSUPPORTED, "avm_run_create: banded majorant needs B = 0");
+  if (o.majorant == AVM_MAJORANT_BANDED && field->dev.has_b && field->dev.kind == FIELD_SLAB)
+    return fail(AVM_E_UNSUPPORTED, "avm_run_create: banded majorant with B needs the polar-map geometry");
   if (o.k_max == 0) o.k_max = (1u << 30) - 1u;
   if (o.k_max > (1u << 30) - 1u) return fail(AVM_E_ARG, "avm_run_create: k_max > 2^30-1");
   if (std::isnan(o.t_max_ns)) return fail(AVM_E_ARG, "avm_run_create: t_max is NaN");

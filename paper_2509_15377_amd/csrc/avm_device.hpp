@@ -39,6 +39,11 @@
 #define AVM_FN __device__ __forceinline__
 #endif
 
+// Channel search: 2 (binary) or 4 (four-way steps, then binary).
+#ifndef AVM_SEARCH_WAYS
+#define AVM_SEARCH_WAYS 2
+#endif
+
 namespace avm {
 
 // electron status codes (non-zero: terminated)
@@ -605,6 +610,62 @@ AVM_FN void signal_end(const SignalDev& Q, const Elec<R>& e) {
   signal_deposit(Q, e.aval, e.sj - 1, weighting<kField>(Q, e.x, e.y, e.z) - e.sphi);
 }
 
+// ---- banded majorant with a magnetic field ----
+// Along a helical flight the energy is not convex in time, so the band rule
+// uses a bound that grows with time.  Along B the speed is at most
+// vp + ap s (vp = |v_par|, ap = |a_par|); across B the velocity is the drift
+// w plus u0 = v_perp - w turned by omega s, which moves away from v_perp by
+// at most |u0| omega s and is never longer than |w| + |u0|.  With p =
+// |v_perp|, q = |u0| omega, m = |w| + |u0|:
+//   2 k_a e(s) <= (vp + ap s)^2 + min(p + q s, m)^2,
+// exact at s = 0.  Evaluated in FP64 in both precisions.
+struct HelixBound {
+  double vp, ap, p, q, m;
+};
+
+AVM_FN HelixBound helix_bound(const FieldDev& F, const RunParams& P, double vx, double vy, double vz,
+                              double Ex, double Ey, double Ez) {
+  const double bx = F.bh[0], by = F.bh[1], bz = F.bh[2];
+  const double vpar = vx * bx + vy * by + vz * bz;
+  const double apar = -P.k_a * (Ex * bx + Ey * by + Ez * bz);
+  const double wx = F.wd_scale * (Ey * F.Bv[2] - Ez * F.Bv[1]);
+  const double wy = F.wd_scale * (Ez * F.Bv[0] - Ex * F.Bv[2]);
+  const double wz = F.wd_scale * (Ex * F.Bv[1] - Ey * F.Bv[0]);
+  const double px = vx - vpar * bx, py = vy - vpar * by, pz = vz - vpar * bz;
+  const double ux = px - wx, uy = py - wy, uz = pz - wz;
+  const double un = sqrt(ux * ux + uy * uy + uz * uz);
+  return HelixBound{fabs(vpar), fabs(apar), sqrt(px * px + py * py + pz * pz), un * F.omega,
+                    sqrt(wx * wx + wy * wy + wz * wz) + un};
+}
+
+// Smallest s >= 0 at which the bound reaches energy e_edge (0 if it is
+// there already, +inf if it never gets there).
+AVM_FN double helix_root(const HelixBound& h, const RunParams& P, double e_edge) {
+  const double T = P.two_ka * e_edge;
+  const double c = T - (h.vp * h.vp + h.p * h.p);
+  if (!(c > 0.0)) return 0.0;
+  // unsaturated branch: (ap^2 + q^2) s^2 + 2 (vp ap + p q) s - c = 0
+  const double A = h.ap * h.ap + h.q * h.q, B = 2.0 * (h.vp * h.ap + h.p * h.q);
+  if (A == 0.0 && B == 0.0) return __builtin_inf();
+  const double s1 = 2.0 * c / (B + sqrt(B * B + 4.0 * A * c));
+  if (h.q == 0.0 || h.p + h.q * s1 <= h.m) return s1;
+  // saturated: (vp + ap s)^2 + m^2 = T, reached after p + q s = m
+  if (h.ap == 0.0 || !(T > h.m * h.m)) return __builtin_inf();
+  return (sqrt(T - h.m * h.m) - h.vp) / h.ap;
+}
+
+// A duration in R no longer than s (a cut time must not overshoot).
+template <class R> AVM_FN R down_to(double s);
+template <> AVM_FN double down_to<double>(double s) { return s; }
+template <> AVM_FN float down_to<float>(double s) {
+#ifdef AVM_HOST_DEBUG
+  float f = (float)s;
+  return (double)f > s ? nextafterf(f, 0.0f) : f;
+#else
+  return __double2float_rd(s);
+#endif
+}
+
 // Smallest s >= 0 at which |v + a s|^2 reaches 2 k_a edge (energy at the band edge).
 template <class R>
 AVM_FN R band_crossing(const RunParams& P, const Elec<R>& e, R ax, R ay, R az, R edge) {
@@ -687,6 +748,33 @@ AVM_FN int decide(const GasDev& G, const TabView<R>& T, R en, R r_sel, R& margin
     const R* row0 = Sel<R>::cum(G) + (size_t)kb * nc;
     const R* row1 = over ? row0 : row0 + nc;
     int lo = 1, hi = nc - 1;  // answer in [lo, hi]
+#if AVM_SEARCH_WAYS == 4
+    // four-way steps while the range is wide: three probes per step, their
+    // gathers issued together (fewer dependent round trips to L2)
+    while (hi - lo >= 4) {
+      const int p1 = lo + ((hi - lo) >> 2), p2 = lo + ((hi - lo) >> 1), p3 = lo + (3 * (hi - lo) >> 2);
+      const R a1 = row0[p1], a2 = row0[p2], a3 = row0[p3];
+      const R b1 = row1[p1], b2 = row1[p2], b3 = row1[p3];
+      const R c1 = over ? a1 : lerp<R>(a1, b1, g1, f);
+      const R c2 = over ? a2 : lerp<R>(a2, b2, g1, f);
+      const R c3 = over ? a3 : lerp<R>(a3, b3, g1, f);
+      const R d1 = Mr::abs_(r_sel - c1), d2 = Mr::abs_(r_sel - c2), d3 = Mr::abs_(r_sel - c3);
+      mg = d1 < mg ? d1 : mg;
+      mg = d2 < mg ? d2 : mg;
+      mg = d3 < mg ? d3 : mg;
+      if (r_sel < c1) {
+        hi = p1;
+      } else if (r_sel < c2) {
+        lo = p1 + 1;
+        hi = p2;
+      } else if (r_sel < c3) {
+        lo = p2 + 1;
+        hi = p3;
+      } else {
+        lo = p3 + 1;
+      }
+    }
+#endif
     while (lo < hi) {
       const int mid = (lo + hi) >> 1;
       const R cm = over ? row0[mid] : lerp<R>(row0[mid], row1[mid], g1, f);
@@ -744,12 +832,31 @@ AVM_FN int32_t flight_step(Elec<R>& e, const GasDev& G, const TabView<R>& T, con
   }
   const R ka = Sel<R>::k_a(P);
   const R ax = -ka * Ex, ay = -ka * Ey, az = -ka * Ez;
+  // banded with B (polar-map geometry): raise the band until the helical
+  // energy bound at the flight start lies below its edge
+  constexpr bool kMayHaveB = !kBanded || kField == FIELD_POLAR;
+  const bool helical = kBanded && kMayHaveB && F.has_b;
+  HelixBound hb{};
+  if (helical) {
+    hb = helix_bound(F, P, (double)e.vx, (double)e.vy, (double)e.vz, (double)Ex, (double)Ey, (double)Ez);
+    while (e.band < G.n_bands - 1 && (hb.vp * hb.vp + hb.p * hb.p) * P.inv_2ka >= (double)T.bedge[e.band])
+      e.band += 1;
+  }
   const R gam = kBanded ? T.bgam[e.band] : Sel<R>::gamma(G);
   const R inv_gam = kBanded ? T.binv[e.band] : Sel<R>::inv_gamma(G);
   const R tau = -Mr::log_(u1) * inv_gam;
   R tau_end = tau;
   int cut = 0;  // 1: band edge, 2: time limit
-  if (kBanded && e.band < G.n_bands - 1) {
+  if (helical) {
+    if (e.band < G.n_bands - 1) {
+      // cut where the energy bound reaches the edge: Gamma_b holds before
+      const double tc = helix_root(hb, P, (double)T.bedge[e.band]);
+      if (tc < (double)tau_end) {
+        tau_end = down_to<R>(tc);
+        cut = 1;
+      }
+    }
+  } else if (kBanded && e.band < G.n_bands - 1) {
     const R fx = Mr::fma(ax, tau, e.vx), fy = Mr::fma(ay, tau, e.vy), fz = Mr::fma(az, tau, e.vz);
     const R edge = T.bedge[e.band];
     if (dot3<R>(fx, fy, fz, fx, fy, fz) * Sel<R>::inv_2ka(P) >= edge) {
@@ -772,10 +879,10 @@ AVM_FN int32_t flight_step(Elec<R>& e, const GasDev& G, const TabView<R>& T, con
   uint32_t side = 0;
   if (kField == FIELD_SLAB) {
     side = slab_exit(e.z, (double)e.vz, (double)az, F.z_lo, F.z_hi, (double)tau_end, s_exit);
-    propagate<R, !kBanded>(F, e, ax, ay, az, Ex, Ey, Ez, side ? (R)s_exit : tau_end, rx, ry, rz, ux, uy, uz);
+    propagate<R, kMayHaveB>(F, e, ax, ay, az, Ex, Ey, Ez, side ? (R)s_exit : tau_end, rx, ry, rz, ux, uy, uz);
     if (side) rz = side == ST_HIGH ? F.z_hi : F.z_lo;
   } else {
-    propagate<R, !kBanded>(F, e, ax, ay, az, Ex, Ey, Ez, tau_end, rx, ry, rz, ux, uy, uz);
+    propagate<R, kMayHaveB>(F, e, ax, ay, az, Ex, Ey, Ez, tau_end, rx, ry, rz, ux, uy, uz);
     const double r2 = rx * rx + ry * ry;
     if (r2 <= F.a2 || r2 >= F.b2) {
       // bisection on the inside/outside predicate (excursions that leave
@@ -785,7 +892,7 @@ AVM_FN int32_t flight_step(Elec<R>& e, const GasDev& G, const TabView<R>& T, con
         const double mid = 0.5 * (lo + hi);
         double mx, my, mz;
         R wx_, wy_, wz_;
-        propagate<R, !kBanded>(F, e, ax, ay, az, Ex, Ey, Ez, (R)mid, mx, my, mz, wx_, wy_, wz_);
+        propagate<R, kMayHaveB>(F, e, ax, ay, az, Ex, Ey, Ez, (R)mid, mx, my, mz, wx_, wy_, wz_);
         const double m2 = mx * mx + my * my;
         if (m2 <= F.a2 || m2 >= F.b2)
           hi = mid;
@@ -793,7 +900,7 @@ AVM_FN int32_t flight_step(Elec<R>& e, const GasDev& G, const TabView<R>& T, con
           lo = mid;
       }
       s_exit = hi;
-      propagate<R, !kBanded>(F, e, ax, ay, az, Ex, Ey, Ez, (R)s_exit, rx, ry, rz, ux, uy, uz);
+      propagate<R, kMayHaveB>(F, e, ax, ay, az, Ex, Ey, Ez, (R)s_exit, rx, ry, rz, ux, uy, uz);
       const double q2 = rx * rx + ry * ry;
       side = q2 <= F.a2 ? ST_WIRE : ST_TUBE;
       const double sc = (side == ST_WIRE ? F.a : F.b) / sqrt(q2);
@@ -801,7 +908,7 @@ AVM_FN int32_t flight_step(Elec<R>& e, const GasDev& G, const TabView<R>& T, con
       ry = ry * sc;
     }
   }
-  if (kSignal) signal_flight<R, !kBanded, kField>(*Q, F, e, ax, ay, az, Ex, Ey, Ez,
+  if (kSignal) signal_flight<R, kMayHaveB, kField>(*Q, F, e, ax, ay, az, Ex, Ey, Ez,
                                                    e.t + (side ? s_exit : (double)tau_end));
   e.x = rx; e.y = ry; e.z = rz;
   e.vx = ux; e.vy = uy; e.vz = uz;

@@ -242,12 +242,12 @@ def highgain(n_aval: int = 256, band_bins: int = 0) -> Workload:
                     "argon-like gas + attachment below 2 eV, 128 um slab, 55 kV/cm")
 
 
-def wire(n_aval: int = 2048) -> Workload:
+def wire(n_aval: int = 2048, band_bins: int = 0) -> Workload:
     phi = np.random.default_rng(5).uniform(0.0, 2.0 * math.pi, 2048)[:n_aval]
     p = primaries_at_rest(n_aval)
     p["x"] = 0.1 * np.cos(phi)
     p["y"] = 0.1 * np.sin(phi)
-    return Workload("wire", argon_like_gas(), wire_polar_map(), p, n_aval, 5,
+    return Workload("wire", argon_like_gas(band_bins=band_bins), wire_polar_map(), p, n_aval, 5,
                     "argon-like gas, wire counter 25 um / 5 mm / 1500 V polar map, 0.5 T axial B")
 
 

@@ -100,3 +100,51 @@ def test_autotune_choice_and_cache(A, oracle_mod, tmp_path):
     for k in ("flights_per_pass", "waves_per_cu", "band_bins"):
         assert res2[k] == res[k]
     assert g2.band_bins == res["band_bins"]
+
+
+def _near_wire(n, seed=7):
+    import math
+    wl = W.wire(n)
+    prim = wl.primaries.copy()
+    phi = np.random.default_rng(seed).uniform(0.0, 2.0 * math.pi, n)
+    prim["x"], prim["y"] = 0.01 * np.cos(phi), 0.01 * np.sin(phi)  # rho = 100 um
+    return wl, prim
+
+
+def test_wire_banded_with_b_against_oracle(A, oracle_mod):
+    """Banded majorant with the 0.5 T field (helical energy bound), per
+    trajectory, on a bounded horizon (the geometry amplifies rounding)."""
+    wl, prim = _near_wire(12)
+    og = oracle_mod.Gas(wl.gas, band_bins=100)
+    ref = oracle_mod.run(og, wl.field, prim, wl.seed, banded=True, k_max=20000)
+    ep, tot, _ = A.run(gas=A.Gas(wl.gas, band_bins=100), field=A.Field(wl.field), primaries=prim,
+                       n_aval=12, seed=wl.seed, majorant=A.BANDED, k_max=20000, capacity=4_000_000,
+                       timeout_s=60.0)
+    rep = CMP.assert_parity(ep, ref)
+    print("wire banded B", rep["matched"], rep["flips"], "band cuts", tot["n_band"])
+    assert tot["n_band"] > 0
+
+
+def test_wire_banded_with_b_matches_global_statistics(A):
+    from scipy import stats
+    n = 2000
+    wl, prim = _near_wire(n, seed=9)
+    g = A.Gas(wl.gas, band_bins=100)
+    f = A.Field(wl.field)
+    out = {}
+    for name, maj in (("global", A.GLOBAL), ("banded", A.BANDED)):
+        r = A.Run(g, f, prim, n, seed=wl.seed, majorant=maj, t_max=3.0, capacity=20_000_000,
+                  timeout_s=100.0)
+        r.execute(); r.sync()
+        c, per = r.counts(), r.avalanche_counts()
+        out[name] = (c, per, r.timing()[0])
+        r.close()
+    (cg, pg, tg), (cb, pb, tb) = out["global"], out["banded"]
+    fl = lambda c: c["n_real"] + c["n_null"] + c["n_masked"] + c["n_band"]
+    print(f"wire near: gain {pg['n_endpoints'].mean():.1f} / {pb['n_endpoints'].mean():.1f}; "
+          f"flights {fl(cg):.3e} / {fl(cb):.3e}; kernel ms {tg:.1f} / {tb:.1f}")
+    a, b = pg["n_endpoints"].astype(float), pb["n_endpoints"].astype(float)
+    assert stats.ks_2samp(a, b).pvalue > 1e-3
+    assert abs(a.mean() - b.mean()) < 4.0 * np.sqrt(a.var() / n + b.var() / n)
+    assert abs(float(cb["n_real"]) - float(cg["n_real"])) / float(cg["n_real"]) < 0.05
+    assert fl(cb) < 0.5 * fl(cg)
