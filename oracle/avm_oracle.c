@@ -865,11 +865,27 @@ static int transport(const ctx_t* cx, elec e, estack* st, orc_endpoint* ep)
     /* with B the band must bound the energy over the whole flight: raise it
      * until the helical bound at the flight start lies below its edge */
     double hb[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    if (helical) {
-      orc_helical_bound(e.v, E, f->B, hb);
+    if (helical) orc_helical_bound(e.v, E, f->B, hb);
+    if (banded && o->band_lookahead > 0.0 && band < g->n_bands - 1) {
+      /* lookahead: the band of the energy after band_lookahead mean free
+       * times of the current band (the flight energy, or its helical bound) */
+      double s_look = o->band_lookahead / g->band_gamma[band];
+      double e_look;
+      if (helical) {
+        double vpar = hb[0] + hb[1] * s_look;
+        double vperp = hb[2] + hb[3] * s_look < hb[4] ? hb[2] + hb[3] * s_look : hb[4];
+        e_look = (vpar * vpar + vperp * vperp) / (2.0 * k_a);
+      } else {
+        double rr[3], vv[3];
+        orc_propagate(e.r, e.v, E, f->B, s_look, rr, vv);
+        e_look = energy_of(vv);
+      }
+      int32_t bl = orc_gas_band_of(g, e_look);
+      if (bl > band) band = bl;
+    }
+    if (helical)
       while (band < g->n_bands - 1 && (hb[0] * hb[0] + hb[2] * hb[2]) / (2.0 * k_a) >= g->band_edge[band])
         band++;
-    }
     double gam = banded ? g->band_gamma[band] : g->gamma;
     double tau = -log(u1) / gam;
     /* the flight ends at the earliest of: the collision candidate, the band
@@ -1163,6 +1179,7 @@ int orc_run_signal(const orc_gas* g, const orc_field* f, const orc_primary* prim
       if (prim[i].aval >= sig->n_rows) return ORC_E_ARG;
   }
   if (o->k_max > (1u << 30) - 1u) return ORC_E_ARG;
+  if (!(o->band_lookahead >= 0.0) || !isfinite(o->band_lookahead)) return ORC_E_ARG;
   if (f->kind == FIELD_SLAB && f->n_E > 1)
     for (uint64_t i = 0; i < n_prim; ++i)
       if (prim[i].aval >= f->n_E) return ORC_E_ARG;

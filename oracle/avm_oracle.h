@@ -105,6 +105,12 @@ typedef struct {
   double t_max_ns;     /* +inf: no time limit */
   uint32_t k_max;      /* flight index limit (<= 2^30-1) */
   int32_t n_threads;   /* 0: all online cores */
+  /* banded majorant: before each flight the band is raised to the band of
+   * the energy the electron would have after band_lookahead mean free times
+   * 1/Gamma_b of its current band (without B the exact flight energy, with B
+   * the helical bound); chosen from the state at the flight start, so the
+   * restart rule keeps the sampling exact.  0: no lookahead. */
+  double band_lookahead;
 } orc_opts;
 
 typedef struct orc_result orc_result;

@@ -50,7 +50,8 @@ class _Channel(C.Structure):
 
 class _Opts(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("banded", C.c_int32), ("fifo", C.c_int32),
-                ("t_max_ns", C.c_double), ("k_max", C.c_uint32), ("n_threads", C.c_int32)]
+                ("t_max_ns", C.c_double), ("k_max", C.c_uint32), ("n_threads", C.c_int32),
+                ("band_lookahead", C.c_double)]
 
 
 class _Signal(C.Structure):
@@ -229,7 +230,8 @@ class Field:
 
 
 def run(gas, field, primaries, seed, *, banded=False, fifo=False, t_max=math.inf,
-        k_max=K_MAX_DEFAULT, threads=0, ids=None, return_threads=False, signal=None):
+        k_max=K_MAX_DEFAULT, threads=0, ids=None, return_threads=False, signal=None,
+        band_lookahead=0.0):
     """Transport the primaries; returns endpoints sorted by (aval, eid).
 
     ``gas``/``field`` are oracle ``Gas``/``Field`` objects or workload
@@ -247,7 +249,8 @@ def run(gas, field, primaries, seed, *, banded=False, fifo=False, t_max=math.inf
     if ids is not None:
         ida = np.ascontiguousarray(ids, dtype=np.uint64)
         idp = ida.ctypes.data_as(C.POINTER(C.c_uint64))
-    o = _Opts(int(seed), int(bool(banded)), int(bool(fifo)), float(t_max), int(k_max), int(threads))
+    o = _Opts(int(seed), int(bool(banded)), int(bool(fifo)), float(t_max), int(k_max), int(threads),
+              float(band_lookahead))
     h = C.c_void_p()
     used = C.c_int32()
     sig = None
