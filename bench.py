@@ -113,6 +113,48 @@ def side_legs(args, make, timed, paths, gas, field, wl, capacity, stream):
     sr.close()
 
 
+def crossover():
+    """Wall time of one whole simulation against the number of avalanches
+    (argon-like gas, one primary each): the GPU (batched, banded, FP64,
+    primaries handed over in host memory, from execute to sync) against the
+    oracle on every host core; the paper reports where the GPU overtakes the
+    CPU (Sec. 4).  Prints one JSON line (not the benchmark line)."""
+    import numpy as np
+    import torch
+
+    from oracle import oracle as O
+    from paper_2509_15377_amd import avm, workloads as W
+
+    full = W.argon(1024, band_bins=100)
+    gas = avm.Gas(full.gas, 0)
+    field = avm.Field(full.field, 0)
+    og = O.Gas(full.gas, band_bins=100)
+    of = O.Field(full.field)
+    rows = []
+    for n in (1, 2, 4, 8, 16, 32, 64, 128, 256, 512, 1024):
+        prim = full.primaries[:n]
+        r = avm.Run(gas, field, prim, n, seed=full.seed, majorant=avm.BANDED, capacity=20_000_000,
+                    timeout_s=120.0)
+        r.execute()
+        r.sync()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(5):
+            t0 = time.perf_counter()
+            r.execute()
+            r.sync()
+            ts.append(time.perf_counter() - t0)
+        electrons = r.counts()["n_endpoints"]
+        r.close()
+        t1 = time.perf_counter()
+        O.run(og, of, prim, full.seed, banded=True)
+        tc = time.perf_counter() - t1
+        rows.append({"avalanches": n, "electrons": int(electrons), "gpu_s": float(np.median(ts)),
+                     "oracle_s": tc})
+    cross = next((r["avalanches"] for r in rows if r["gpu_s"] < r["oracle_s"]), None)
+    print(json.dumps({"crossover": rows, "gpu_faster_from_avalanches": cross}), flush=True)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -126,6 +168,8 @@ def parse():
                     help="launch the batched run eagerly instead of replaying its HIP graph")
     ap.add_argument("--headline-only", action="store_true",
                     help="time only the headline path (for counter passes)")
+    ap.add_argument("--crossover", action="store_true",
+                    help="only measure the CPU/GPU crossover in the number of avalanches")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration)")
     return ap.parse_args()
@@ -139,6 +183,9 @@ def main():
         sys.exit(2)
     if args.copy_probe:
         copy_probe()
+        return
+    if args.crossover:
+        crossover()
         return
     if args.headline_only:
         args.no_mixed = args.no_plain = args.no_cpu = True

@@ -176,7 +176,10 @@ typedef struct {
   int32_t graph;          /* batched: 1 = capture the run's device work (reset, primary  */
                           /*   load, transport, statistics, result copies) into a HIP    */
                           /*   graph on the first execute and replay it afterwards       */
-  int32_t _pad1;
+  float band_lookahead;   /* banded: before each flight the band is raised to the band   */
+                          /*   of the energy after this many mean free times of the      */
+                          /*   current band (flight energy; with B its helical bound);   */
+                          /*   the restart rule keeps sampling exact; 0: none; >= 0      */
 } avm_run_opts;
 
 /* One electron's record.  status: 1 left z_lo, 2 left z_hi, 3 attached,
@@ -284,7 +287,7 @@ typedef struct {
   int32_t band_bins;        /* band width the gas is left with                          */
   int32_t trials;           /* configurations timed (0 when taken from the cache)       */
   int32_t from_cache;       /* 1 when cache_path already held this workload's choice    */
-  int32_t _pad;
+  float band_lookahead;     /* chosen band lookahead (banded; results depend on it)     */
   double best_ms;           /* transport-kernel ms of the chosen configuration (cache:  */
                             /*   as recorded)                                           */
   double start_ms;          /* transport-kernel ms of the starting configuration        */
@@ -292,7 +295,8 @@ typedef struct {
 } avm_tune_result;
 
 /* Choose flights_per_pass, waves_per_cu and (with AVM_TUNE_BANDS and the
- * banded majorant) the gas's band width for a batched run of these
+ * banded majorant) the gas's band width and the band lookahead for a
+ * batched run of these
  * primaries: a coordinate search over candidate values, each timed on the
  * device (HIP events around the transport kernel, best of two executions
  * after one warm-up).  The trials run the given primaries in full, so for a
@@ -302,8 +306,8 @@ typedef struct {
  * ignored).  cache_path (may be NULL): a text file of earlier choices; a
  * line with this workload's key is used without trials, a new choice is
  * appended.  The gas is left with the chosen band width.  Results of runs
- * depend on the band width (other random draws), not on flights_per_pass or
- * waves_per_cu.  Errors: AVM_E_ARG as avm_run_create, or a mode other than
+ * depend on the band width and lookahead (other random draws), not on
+ * flights_per_pass or waves_per_cu.  Errors: AVM_E_ARG as avm_run_create, or a mode other than
  * batched; any error of the trial runs. */
 avm_status avm_autotune(avm_gas* gas, const avm_field* field, const avm_primary* prim,
                         int32_t prim_on_device, uint64_t n_prim, uint32_t n_aval,

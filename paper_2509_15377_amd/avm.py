@@ -58,7 +58,7 @@ class _Opts(C.Structure):
                 ("mode", C.c_int32), ("flights_per_pass", C.c_int32), ("t_max_ns", C.c_double),
                 ("capacity", C.c_uint64), ("k_max", C.c_uint32), ("waves_per_cu", C.c_int32),
                 ("timeout_s", C.c_double), ("hip_stream", C.c_void_p), ("graph", C.c_int32),
-                ("_pad1", C.c_int32)]
+                ("band_lookahead", C.c_float)]
 
 
 class _Counts(C.Structure):
@@ -71,7 +71,7 @@ class _Counts(C.Structure):
 class _TuneResult(C.Structure):
     _fields_ = [("flights_per_pass", C.c_int32), ("waves_per_cu", C.c_int32),
                 ("band_bins", C.c_int32), ("trials", C.c_int32), ("from_cache", C.c_int32),
-                ("_pad", C.c_int32), ("best_ms", C.c_double), ("start_ms", C.c_double),
+                ("band_lookahead", C.c_float), ("best_ms", C.c_double), ("start_ms", C.c_double),
                 ("key", C.c_uint64)]
 
 
@@ -273,13 +273,13 @@ def _primaries_arg(primaries):
 
 
 def _make_opts(seed, precision, majorant, mode, flights_per_pass, t_max, capacity, k_max,
-               waves_per_cu, timeout_s, stream, graph):
+               waves_per_cu, timeout_s, stream, graph, band_lookahead=0.0):
     st = None
     if stream is not None:
         st = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
     return _Opts(int(seed), precision, majorant, mode, int(flights_per_pass), float(t_max),
                  int(capacity), int(k_max), int(waves_per_cu), float(timeout_s), st,
-                 int(bool(graph)), 0)
+                 int(bool(graph)), float(band_lookahead))
 
 
 def autotune(gas: Gas, field: Field, primaries, n_aval: int, *, seed: int, precision=FP64,
@@ -287,7 +287,7 @@ def autotune(gas: Gas, field: Field, primaries, n_aval: int, *, seed: int, preci
              tune_bands=True, cache=None):
     """Choose flights_per_pass, waves_per_cu and (banded) the gas's band
     width for a batched run of these primaries (avm_autotune).  Returns a
-    dict; pass its flights_per_pass and waves_per_cu to Run."""
+    dict; pass its flights_per_pass, waves_per_cu and band_lookahead to Run."""
     ptr, on_dev, n_prim, keep = _primaries_arg(primaries)
     o = _make_opts(seed, precision, majorant, BATCHED, 0, t_max, capacity, k_max, 0, timeout_s,
                    stream, False)
@@ -308,12 +308,12 @@ class Run:
     def __init__(self, gas: Gas, field: Field, primaries, n_aval: int, *, seed: int,
                  precision=FP64, majorant=GLOBAL, mode=BATCHED, capacity=0, t_max=math.inf,
                  k_max=0, flights_per_pass=0, waves_per_cu=0, timeout_s=0.0, stream=None,
-                 graph=False):
+                 graph=False, band_lookahead=0.0):
         self._keep = [gas, field, primaries]
         ptr, on_dev, n_prim, keep = _primaries_arg(primaries)
         self._keep.append(keep)
         o = _make_opts(seed, precision, majorant, mode, flights_per_pass, t_max, capacity, k_max,
-                       waves_per_cu, timeout_s, stream, graph)
+                       waves_per_cu, timeout_s, stream, graph, band_lookahead)
         h = _VP()
         _check(lib().avm_run_create(gas.h, field.h, ptr, on_dev, n_prim, int(n_aval), C.byref(o),
                                     C.byref(h)), "avm_run_create")

@@ -624,6 +624,8 @@ avm_status avm_run_create(const avm_gas* gas, const avm_field* field, const avm_
   if (o.capacity > 0xFFFFFFF0ull) return fail(AVM_E_ARG, "avm_run_create: capacity above 2^32-16");
   if (o.flights_per_pass <= 0) o.flights_per_pass = 64;
   if (o.waves_per_cu < 0) return fail(AVM_E_ARG, "avm_run_create: waves_per_cu < 0");
+  if (!(o.band_lookahead >= 0.0f) || !std::isfinite(o.band_lookahead))
+    return fail(AVM_E_ARG, "avm_run_create: band_lookahead must be finite and >= 0");
   if (o.graph && o.mode != AVM_MODE_BATCHED)
     return fail(AVM_E_ARG, "avm_run_create: graph capture needs the batched mode (the plain mode reads the host)");
   if (!prim_on_device)
@@ -702,6 +704,7 @@ static RunParams run_params(const avm_run* r) {
   // a hard cap; a kernel past it stops and the run reports AVM_E_TIMEOUT
   const double budget_s = r->opts.timeout_s > 0.0 ? r->opts.timeout_s : 600.0;
   P.budget_ticks = (uint64_t)(budget_s * 1e3 * (double)r->clock_khz);
+  P.look = r->opts.majorant == AVM_MAJORANT_BANDED ? (double)r->opts.band_lookahead : 0.0;
   return P;
 }
 
@@ -1087,7 +1090,7 @@ hipError_t tune_key(const avm_gas* g, const avm_field* fl, const avm_primary* pr
   return e;
 }
 
-bool cache_lookup(const char* path, uint64_t key, int* fpp, int* wpc, int* bb, double* ms) {
+bool cache_lookup(const char* path, uint64_t key, int* fpp, int* wpc, int* bb, float* look, double* ms) {
   if (!path) return false;
   std::FILE* fp = std::fopen(path, "r");
   if (!fp) return false;
@@ -1096,9 +1099,10 @@ bool cache_lookup(const char* path, uint64_t key, int* fpp, int* wpc, int* bb, d
   while (std::fgets(line, sizeof line, fp)) {
     unsigned long long k = 0;
     int a = 0, b = 0, c = 0;
+    float l = 0.0f;
     double t = 0.0;
-    if (std::sscanf(line, "avm_tune 1 %llx %d %d %d %lf", &k, &a, &b, &c, &t) == 5 && k == key) {
-      *fpp = a; *wpc = b; *bb = c; *ms = t;
+    if (std::sscanf(line, "avm_tune 2 %llx %d %d %d %f %lf", &k, &a, &b, &c, &l, &t) == 6 && k == key) {
+      *fpp = a; *wpc = b; *bb = c; *look = l; *ms = t;
       found = true;  // the last matching line wins
     }
   }
@@ -1129,8 +1133,9 @@ extern "C" avm_status avm_autotune(avm_gas* gas, const avm_field* field, const a
   out->key = key;
   {
     int fpp = 0, wpc = 0, bb = 0;
+    float look = 0.0f;
     double ms = 0.0;
-    if (cache_lookup(cache_path, key, &fpp, &wpc, &bb, &ms)) {
+    if (cache_lookup(cache_path, key, &fpp, &wpc, &bb, &look, &ms)) {
       if (tune_bands && bb != gas->band_bins) {
         const avm_status st = avm_gas_set_band_bins(gas, bb);
         if (st != AVM_OK) return st;
@@ -1138,6 +1143,7 @@ extern "C" avm_status avm_autotune(avm_gas* gas, const avm_field* field, const a
       out->flights_per_pass = fpp;
       out->waves_per_cu = wpc;
       out->band_bins = gas->band_bins;
+      out->band_lookahead = look;
       out->from_cache = 1;
       out->best_ms = ms;
       out->start_ms = ms;
@@ -1156,14 +1162,14 @@ extern "C" avm_status avm_autotune(avm_gas* gas, const avm_field* field, const a
       return fail(AVM_E_HIP, "avm_autotune: %s", hipGetErrorString(e));
     }
   }
-  struct Trial { int fpp, wpc, bb; double ms; };
+  struct Trial { int fpp, wpc, bb; float look; double ms; };
   std::vector<Trial> done;
   bool warm = false;
   // best of two timed executions (after one warm-up execution of the run)
-  auto measure = [&](int fpp, int wpc, int bb, double* ms) -> avm_status {
+  auto measure = [&](int fpp, int wpc, int bb, float look, double* ms) -> avm_status {
     if (fpp < 1) return fail(AVM_E_ARG, "avm_autotune: flights per pass %d < 1", fpp);
     for (const Trial& t : done)
-      if (t.fpp == fpp && t.wpc == wpc && t.bb == bb) {
+      if (t.fpp == fpp && t.wpc == wpc && t.bb == bb && t.look == look) {
         *ms = t.ms;
         return AVM_OK;
       }
@@ -1173,6 +1179,7 @@ extern "C" avm_status avm_autotune(avm_gas* gas, const avm_field* field, const a
     }
     r->opts.flights_per_pass = fpp;
     r->opts.waves_per_cu = wpc;
+    r->opts.band_lookahead = look;
     const hipError_t e = batched_grid(r, wpc, &r->grid, nullptr);
     if (e != hipSuccess) return fail(AVM_E_HIP, "avm_autotune: %s", hipGetErrorString(e));
     double best = INFINITY;
@@ -1186,7 +1193,7 @@ extern "C" avm_status avm_autotune(avm_gas* gas, const avm_field* field, const a
       if (rep >= 0 && t < best) best = t;
     }
     warm = true;
-    done.push_back({fpp, wpc, bb, best});
+    done.push_back({fpp, wpc, bb, look, best});
     *ms = best;
     return AVM_OK;
   };
@@ -1197,23 +1204,30 @@ extern "C" avm_status avm_autotune(avm_gas* gas, const avm_field* field, const a
       if (b < gas->n_bins && b != bb0) bands.push_back(b);
   std::vector<int> wpcs = {0};
   for (int j = 1; j < max_blocks; ++j) wpcs.push_back(j * (r->block / 64));
-  Trial best{o.flights_per_pass, o.waves_per_cu, bb0, INFINITY};
-  st = measure(best.fpp, best.wpc, best.bb, &best.ms);
+  std::vector<float> looks = {o.band_lookahead};
+  if (tune_bands)
+    for (float l : {0.0f, 0.5f, 1.0f, 2.0f})
+      if (l != o.band_lookahead) looks.push_back(l);
+  Trial best{o.flights_per_pass, o.waves_per_cu, bb0, o.band_lookahead, INFINITY};
+  st = measure(best.fpp, best.wpc, best.bb, best.look, &best.ms);
   if (st == AVM_OK) out->start_ms = best.ms;
-  auto consider = [&](int fpp, int wpc, int bb) {
+  auto consider = [&](int fpp, int wpc, int bb, float look) {
     if (st != AVM_OK) return;
     double ms = 0.0;
-    st = measure(fpp, wpc, bb, &ms);
-    if (st == AVM_OK && ms < best.ms) best = {fpp, wpc, bb, ms};
+    st = measure(fpp, wpc, bb, look, &ms);
+    if (st == AVM_OK && ms < best.ms) best = {fpp, wpc, bb, look, ms};
   };
-  // coordinate search: flights per pass, band width, flights per pass
-  // around the best again, resident waves
-  for (int f : fpps) consider(f, best.wpc, best.bb);
-  for (int b : bands) consider(best.fpp, best.wpc, b);
+  // coordinate search: flights per pass, band width, lookahead, band width
+  // again at the chosen lookahead, flights per pass around the best,
+  // resident waves
+  for (int f : fpps) consider(f, best.wpc, best.bb, best.look);
+  for (int b : bands) consider(best.fpp, best.wpc, b, best.look);
+  for (float l : looks) consider(best.fpp, best.wpc, best.bb, l);
+  for (int b : bands) consider(best.fpp, best.wpc, b, best.look);
   const int f0 = best.fpp;
   for (int f : {f0 / 2, f0 * 2})
-    if (f >= 4 && f <= 256) consider(f, best.wpc, best.bb);
-  for (int w : wpcs) consider(best.fpp, w, best.bb);
+    if (f >= 4 && f <= 256) consider(f, best.wpc, best.bb, best.look);
+  for (int w : wpcs) consider(best.fpp, w, best.bb, best.look);
   avm_run_destroy(r);
   if (st == AVM_OK && best.bb != gas->band_bins) st = avm_gas_set_band_bins(gas, best.bb);
   if (st != AVM_OK) {
@@ -1225,13 +1239,14 @@ extern "C" avm_status avm_autotune(avm_gas* gas, const avm_field* field, const a
   out->flights_per_pass = best.fpp;
   out->waves_per_cu = best.wpc;
   out->band_bins = best.bb;
+  out->band_lookahead = best.look;
   out->trials = (int32_t)done.size();
   out->best_ms = best.ms;
   if (cache_path) {
     std::FILE* fp = std::fopen(cache_path, "a");
     if (!fp) return fail(AVM_E_ARG, "avm_autotune: cannot append to %s", cache_path);
-    std::fprintf(fp, "avm_tune 1 %016llx %d %d %d %.6f\n", (unsigned long long)key, best.fpp, best.wpc,
-                 best.bb, best.ms);
+    std::fprintf(fp, "avm_tune 2 %016llx %d %d %d %.3f %.6f\n", (unsigned long long)key, best.fpp,
+                 best.wpc, best.bb, (double)best.look, best.ms);
     std::fclose(fp);
   }
   return AVM_OK;

@@ -139,6 +139,7 @@ struct RunParams {
   double k_a, two_ka, inv_2ka;
   float k_a_f, two_ka_f, inv_2ka_f, _padf;
   uint64_t budget_ticks;    // wall_clock64() ticks a transport kernel may run
+  double look;              // banded: band lookahead in mean free times (0: none)
 };
 
 // Induced signal on the readout electrode (Shockley-Ramo): bin j of
@@ -837,11 +838,30 @@ AVM_FN int32_t flight_step(Elec<R>& e, const GasDev& G, const TabView<R>& T, con
   constexpr bool kMayHaveB = !kBanded || kField == FIELD_POLAR;
   const bool helical = kBanded && kMayHaveB && F.has_b;
   HelixBound hb{};
-  if (helical) {
+  if (helical)
     hb = helix_bound(F, P, (double)e.vx, (double)e.vy, (double)e.vz, (double)Ex, (double)Ey, (double)Ez);
+  if (kBanded && P.look > 0.0 && e.band < G.n_bands - 1) {
+    // lookahead: raise the band to the band of the energy after `look` mean
+    // free times of the current band (the flight energy, or its helical
+    // bound); the choice uses only the state at the flight start
+    const double s_look = P.look * (double)T.binv[e.band];
+    R e_look;
+    if (helical) {
+      const double vpar = hb.vp + hb.ap * s_look;
+      const double lin = hb.p + hb.q * s_look;
+      const double vperp = lin < hb.m ? lin : hb.m;
+      e_look = (R)((vpar * vpar + vperp * vperp) * P.inv_2ka);
+    } else {
+      const R sl = (R)s_look;
+      const R fx = Mr::fma(ax, sl, e.vx), fy = Mr::fma(ay, sl, e.vy), fz = Mr::fma(az, sl, e.vz);
+      e_look = dot3<R>(fx, fy, fz, fx, fy, fz) * Sel<R>::inv_2ka(P);
+    }
+    const int32_t bl = band_of<R>(G, T, e_look);
+    if (bl > e.band) e.band = bl;
+  }
+  if (helical)
     while (e.band < G.n_bands - 1 && (hb.vp * hb.vp + hb.p * hb.p) * P.inv_2ka >= (double)T.bedge[e.band])
       e.band += 1;
-  }
   const R gam = kBanded ? T.bgam[e.band] : Sel<R>::gamma(G);
   const R inv_gam = kBanded ? T.binv[e.band] : Sel<R>::inv_gamma(G);
   const R tau = -Mr::log_(u1) * inv_gam;

@@ -79,10 +79,11 @@ def test_autotune_choice_and_cache(A, oracle_mod, tmp_path):
     assert g.band_bins == res["band_bins"]
     assert cache.read_text().count("avm_tune 1") == 1
     # launch parameters do not change results: tuned == default at that band width
+    look = res["band_lookahead"]
     tuned = A.Run(g, f, wl.primaries, wl.n_aval, flights_per_pass=res["flights_per_pass"],
-                  waves_per_cu=res["waves_per_cu"], **kw)
+                  waves_per_cu=res["waves_per_cu"], band_lookahead=look, **kw)
     tuned.execute(); tuned.sync()
-    plain = A.Run(g, f, wl.primaries, wl.n_aval, **kw)
+    plain = A.Run(g, f, wl.primaries, wl.n_aval, band_lookahead=look, **kw)
     plain.execute(); plain.sync()
     a, b = _sorted(tuned.endpoints()), _sorted(plain.endpoints())
     assert a.tobytes() == b.tobytes()
@@ -91,13 +92,13 @@ def test_autotune_choice_and_cache(A, oracle_mod, tmp_path):
     # the chosen band width against the oracle built with it
     sub = wl.primaries[wl.primaries["aval"] < 10]
     ref = oracle_mod.run(oracle_mod.Gas(wl.gas, band_bins=res["band_bins"]), wl.field, sub, wl.seed,
-                         banded=True)
+                         banded=True, band_lookahead=look)
     print("tuned bands", CMP.assert_parity(a[a["aval"] < 10], ref))
     # second call: from the cache, no trials, same choice, gas set to it
     g2 = A.Gas(wl.gas, band_bins=100)
     res2 = A.autotune(g2, f, wl.primaries, wl.n_aval, cache=str(cache), **kw)
     assert res2["from_cache"] == 1 and res2["trials"] == 0 and res2["key"] == res["key"]
-    for k in ("flights_per_pass", "waves_per_cu", "band_bins"):
+    for k in ("flights_per_pass", "waves_per_cu", "band_bins", "band_lookahead"):
         assert res2[k] == res[k]
     assert g2.band_bins == res["band_bins"]
 
@@ -148,3 +149,34 @@ def test_wire_banded_with_b_matches_global_statistics(A):
     assert abs(a.mean() - b.mean()) < 4.0 * np.sqrt(a.var() / n + b.var() / n)
     assert abs(float(cb["n_real"]) - float(cg["n_real"])) / float(cg["n_real"]) < 0.05
     assert fl(cb) < 0.5 * fl(cg)
+
+
+@pytest.mark.parametrize("look", [0.5, 1.0])
+def test_band_lookahead_against_oracle(A, oracle_mod, look):
+    wl = W.argon(40)
+    ref = oracle_mod.run(oracle_mod.Gas(wl.gas, band_bins=100), wl.field, wl.primaries, wl.seed,
+                         banded=True, band_lookahead=look)
+    ep, tot, _ = A.run(wl, band_bins=100, majorant=A.BANDED, band_lookahead=look, capacity=4_000_000,
+                       timeout_s=60.0)
+    rep = CMP.assert_parity(ep, ref)
+    fl = tot["n_real"] + tot["n_null"] + tot["n_masked"] + tot["n_band"]
+    print("lookahead", look, rep["matched"], rep["flips"], "flights/real", fl / tot["n_real"])
+
+
+def test_band_lookahead_wire_with_b_against_oracle(A, oracle_mod):
+    wl, prim = _near_wire(12, seed=23)
+    ref = oracle_mod.run(oracle_mod.Gas(wl.gas, band_bins=100), wl.field, prim, wl.seed, banded=True,
+                         k_max=20000, band_lookahead=1.0)
+    ep, _, _ = A.run(gas=A.Gas(wl.gas, band_bins=100), field=A.Field(wl.field), primaries=prim,
+                     n_aval=12, seed=wl.seed, majorant=A.BANDED, k_max=20000, band_lookahead=1.0,
+                     capacity=4_000_000, timeout_s=60.0)
+    CMP.assert_parity(ep, ref)
+
+
+def test_band_lookahead_rejects_bad_values(A):
+    wl = W.toy(2)
+    g, f = A.Gas(wl.gas, band_bins=100), A.Field(wl.field)
+    for bad in (-1.0, float("nan"), float("inf")):
+        with pytest.raises(A.AvmError) as e:
+            A.Run(g, f, wl.primaries, 2, seed=1, majorant=A.BANDED, band_lookahead=bad)
+        assert e.value.status == A.AVM_E_ARG
