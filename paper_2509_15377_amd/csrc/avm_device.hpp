@@ -667,17 +667,19 @@ template <> AVM_FN float down_to<float>(double s) {
 #endif
 }
 
-// Smallest s >= 0 at which |v + a s|^2 reaches 2 k_a edge (energy at the band edge).
+// Smallest s >= 0 at which |v + a s|^2 reaches 2 k_a edge (energy at the band
+// edge).  The energy starts below the edge (C < 0), so with A = |a|^2 > 0 the
+// quadratic has one positive root; its stable form needs one division (the
+// same bits as the positive root of the general stable solver).
 template <class R>
 AVM_FN R band_crossing(const RunParams& P, const Elec<R>& e, R ax, R ay, R az, R edge) {
   const R C = dot3<R>(e.vx, e.vy, e.vz, e.vx, e.vy, e.vz) - Sel<R>::two_ka(P) * edge;
   if (C >= R(0)) return R(0);
-  R r1 = R(0), r2 = R(0);
-  const int n = roots2<R>(dot3<R>(ax, ay, az, ax, ay, az), R(2) * dot3<R>(e.vx, e.vy, e.vz, ax, ay, az),
-                          C, r1, r2);
-  if (n >= 1 && r1 >= R(0)) return r1;
-  if (n == 2 && r2 >= R(0)) return r2;
-  return R(0);
+  const R A = dot3<R>(ax, ay, az, ax, ay, az);
+  if (A == R(0)) return R(0);
+  const R B = R(2) * dot3<R>(e.vx, e.vy, e.vz, ax, ay, az);
+  const R sq = M<R>::sqrt_(B * B - R(4) * A * C);
+  return B > R(0) ? (R(-2) * C) / (B + sq) : (sq - B) / (R(2) * A);
 }
 
 // New velocity after a real collision: the old direction turned by

@@ -77,7 +77,7 @@ def test_autotune_choice_and_cache(A, oracle_mod, tmp_path):
     assert res["trials"] >= 8 and res["from_cache"] == 0
     assert res["best_ms"] <= res["start_ms"]
     assert g.band_bins == res["band_bins"]
-    assert cache.read_text().count("avm_tune 1") == 1
+    assert cache.read_text().count("avm_tune 2") == 1
     # launch parameters do not change results: tuned == default at that band width
     look = res["band_lookahead"]
     tuned = A.Run(g, f, wl.primaries, wl.n_aval, flights_per_pass=res["flights_per_pass"],
@@ -112,15 +112,22 @@ def _near_wire(n, seed=7):
     return wl, prim
 
 
+# Near the wire (strong field, 0.5 T) a one-ulp difference grows tenfold
+# every ~300 flights (a CPU build of the device step against the oracle:
+# 1e-16 after 2 flights, 4e-13 after 1200, 6e-9 after 2500), so the
+# per-trajectory comparisons there stop every electron after 1000 flights.
+NEAR_WIRE_K_MAX = 1000
+
+
 def test_wire_banded_with_b_against_oracle(A, oracle_mod):
     """Banded majorant with the 0.5 T field (helical energy bound), per
     trajectory, on a bounded horizon (the geometry amplifies rounding)."""
     wl, prim = _near_wire(12)
     og = oracle_mod.Gas(wl.gas, band_bins=100)
-    ref = oracle_mod.run(og, wl.field, prim, wl.seed, banded=True, k_max=20000)
+    ref = oracle_mod.run(og, wl.field, prim, wl.seed, banded=True, k_max=NEAR_WIRE_K_MAX)
     ep, tot, _ = A.run(gas=A.Gas(wl.gas, band_bins=100), field=A.Field(wl.field), primaries=prim,
-                       n_aval=12, seed=wl.seed, majorant=A.BANDED, k_max=20000, capacity=4_000_000,
-                       timeout_s=60.0)
+                       n_aval=12, seed=wl.seed, majorant=A.BANDED, k_max=NEAR_WIRE_K_MAX,
+                       capacity=4_000_000, timeout_s=60.0)
     rep = CMP.assert_parity(ep, ref)
     print("wire banded B", rep["matched"], rep["flips"], "band cuts", tot["n_band"])
     assert tot["n_band"] > 0
@@ -166,9 +173,10 @@ def test_band_lookahead_against_oracle(A, oracle_mod, look):
 def test_band_lookahead_wire_with_b_against_oracle(A, oracle_mod):
     wl, prim = _near_wire(12, seed=23)
     ref = oracle_mod.run(oracle_mod.Gas(wl.gas, band_bins=100), wl.field, prim, wl.seed, banded=True,
-                         k_max=20000, band_lookahead=1.0)
+                         k_max=NEAR_WIRE_K_MAX, band_lookahead=1.0)
     ep, _, _ = A.run(gas=A.Gas(wl.gas, band_bins=100), field=A.Field(wl.field), primaries=prim,
-                     n_aval=12, seed=wl.seed, majorant=A.BANDED, k_max=20000, band_lookahead=1.0,
+                     n_aval=12, seed=wl.seed, majorant=A.BANDED, k_max=NEAR_WIRE_K_MAX,
+                     band_lookahead=1.0,
                      capacity=4_000_000, timeout_s=60.0)
     CMP.assert_parity(ep, ref)
 
