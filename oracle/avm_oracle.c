@@ -96,6 +96,7 @@ struct orc_gas {
   int32_t band_bins, n_bands;
   double *band_gamma; /* [n_bands] */
   double *band_edge;  /* [n_bands] upper energy edge; +inf for the last */
+  double *penning_prob, *penning_e; /* [n_ch] Penning transfer of excitations */
 };
 
 static void gas_free(orc_gas* g)
@@ -105,6 +106,7 @@ static void gas_free(orc_gas* g)
   free(g->loss); free(g->e_lo); free(g->e_hi); free(g->mass_ratio); free(g->split_w);
   free(g->screening); free(g->cum); free(g->total); free(g->binmax);
   free(g->band_gamma); free(g->band_edge);
+  free(g->penning_prob); free(g->penning_e);
   free(g);
 }
 
@@ -141,11 +143,14 @@ int orc_gas_create(double e_max_eV, int32_t n_bins, double density_cm3, int32_t 
   g->mass_ratio = calloc(n_ch, sizeof(double));
   g->split_w = calloc(n_ch, sizeof(double));
   g->screening = calloc(n_ch, sizeof(double));
+  g->penning_prob = calloc(n_ch, sizeof(double));
+  g->penning_e = calloc(n_ch, sizeof(double));
   g->cum = calloc(nn * (size_t)n_ch, sizeof(double));
   g->total = calloc(nn, sizeof(double));
   g->binmax = calloc((size_t)n_bins, sizeof(double));
   if (!g->kind || !g->angular || !g->split || !g->loss || !g->e_lo || !g->e_hi ||
-      !g->mass_ratio || !g->split_w || !g->screening || !g->cum || !g->total || !g->binmax) {
+      !g->mass_ratio || !g->split_w || !g->screening || !g->cum || !g->total || !g->binmax ||
+      !g->penning_prob || !g->penning_e) {
     gas_free(g);
     return ORC_E_NOMEM;
   }
@@ -216,6 +221,19 @@ int orc_gas_create(double e_max_eV, int32_t n_bins, double density_cm3, int32_t 
     g->band_edge[b] = ((double)kend * e_max_eV) / (double)n_bins;
   }
   *out = g;
+  return ORC_OK;
+}
+
+/* Penning transfer (reading): an excitation in channel c is followed, with
+ * probability prob, by an extra electron of energy energy_eV born where the
+ * excitation happened (the excitation energy ionising another molecule).
+ * Excitation channels only. */
+int orc_gas_set_penning(orc_gas* g, int32_t c, double prob, double energy_eV)
+{
+  if (!g || c < 0 || c >= g->n_ch || g->kind[c] != ORC_EXCITATION) return ORC_E_ARG;
+  if (!(prob >= 0.0 && prob <= 1.0) || !(energy_eV >= 0.0) || !isfinite(energy_eV)) return ORC_E_ARG;
+  g->penning_prob[c] = prob;
+  g->penning_e[c] = energy_eV;
   return ORC_OK;
 }
 
@@ -820,6 +838,28 @@ static void direction_of(const double v[3], double d[3])
   }
 }
 
+/* Push a secondary electron of energy e_s born at the parent's position and
+ * time, direction isotropic from (uC, uP), id `child`. */
+static int push_secondary(estack* st, const elec* parent, double e_s, double uC, double uP, uint64_t child)
+{
+  double ct = 1.0 - 2.0 * uC;
+  double st2 = 1.0 - ct * ct;
+  double stt = st2 > 0.0 ? sqrt(st2) : 0.0;
+  double ph2 = TWO_PI * uP;
+  double ds[3] = {stt * cos(ph2), stt * sin(ph2), ct};
+  elec s;
+  s.r[0] = parent->r[0]; s.r[1] = parent->r[1]; s.r[2] = parent->r[2];
+  set_velocity(s.v, e_s, ds);
+  s.t = parent->t;
+  s.r0[0] = parent->r[0]; s.r0[1] = parent->r[1]; s.r0[2] = parent->r[2];
+  s.t0 = parent->t;
+  s.e0 = e_s;
+  s.eid = child;
+  s.parent = parent->eid;
+  s.aval = parent->aval;
+  return estack_push(st, &s);
+}
+
 /* Carry one electron through the loop of Fig. 2 until it terminates.  Each
  * pass: position valid? -> field at r, random flight time -> boundary, time
  * limit or band edge within the flight? -> collision? (real or null) ->
@@ -1028,6 +1068,18 @@ static int transport(const ctx_t* cx, elec e, estack* st, orc_endpoint* ep)
     } else if (g->kind[c] == ORC_EXCITATION) {
       e_new = en - g->loss[c];
       orc_rotate(d, 1.0 - 2.0 * uA, phi, dn);
+      if (g->penning_prob[c] > 0.0) {
+        /* Penning transfer: blocks j = 2, 3 as for an ionisation */
+        uint32_t w2[4], w3[4];
+        draw(o->seed, e.aval, e.eid, k, 2, w2);
+        if (orc_u53(w2[0], w2[1]) < g->penning_prob[c]) {
+          draw(o->seed, e.aval, e.eid, k, 3, w3);
+          uint64_t child = (((uint64_t)w3[3] << 32) | (uint64_t)w3[2]) & 0x7FFFFFFFFFFFFFFFull;
+          if (push_secondary(st, &e, g->penning_e[c], orc_u53(w2[2], w2[3]), orc_u53(w3[0], w3[1]), child) != ORC_OK)
+            return ORC_E_NOMEM;
+          ep->n_ion++;
+        }
+      }
     } else { /* ionisation */
       double e_avail = en - g->loss[c];
       uint32_t w2[4], w3[4];
@@ -1041,22 +1093,7 @@ static int transport(const ctx_t* cx, elec e, estack* st, orc_endpoint* ep)
       e_new = e_avail - e_s;
       orc_rotate(d, 1.0 - 2.0 * uA, phi, dn);
       /* the secondary starts where the ionisation happened, isotropically */
-      double ct = 1.0 - 2.0 * uC;
-      double st2 = 1.0 - ct * ct;
-      double stt = st2 > 0.0 ? sqrt(st2) : 0.0;
-      double ph2 = TWO_PI * uP;
-      double ds[3] = {stt * cos(ph2), stt * sin(ph2), ct};
-      elec s;
-      s.r[0] = e.r[0]; s.r[1] = e.r[1]; s.r[2] = e.r[2];
-      set_velocity(s.v, e_s, ds);
-      s.t = e.t;
-      s.r0[0] = e.r[0]; s.r0[1] = e.r[1]; s.r0[2] = e.r[2];
-      s.t0 = e.t;
-      s.e0 = e_s;
-      s.eid = child;
-      s.parent = e.eid;
-      s.aval = e.aval;
-      if (estack_push(st, &s) != ORC_OK) return ORC_E_NOMEM;
+      if (push_secondary(st, &e, e_s, uC, uP, child) != ORC_OK) return ORC_E_NOMEM;
       ep->n_ion++;
     }
     set_velocity(e.v, e_new, dn);

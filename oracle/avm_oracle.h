@@ -63,6 +63,11 @@ typedef struct orc_field orc_field;
 int orc_gas_create(double e_max_eV, int32_t n_bins, double density_cm3, int32_t n_ch,
                    const orc_channel* ch, int32_t band_bins, orc_gas** out);
 void orc_gas_destroy(orc_gas*);
+/* Penning transfer of excitation channel c: with probability prob an
+ * excitation is followed by an extra electron of energy energy_eV born
+ * where it happened, isotropic (random blocks j = 2, 3 of the flight, as
+ * for an ionisation; it counts as a secondary in n_ion). */
+int orc_gas_set_penning(orc_gas*, int32_t channel, double prob, double energy_eV);
 double orc_gas_gamma(const orc_gas*);
 int32_t orc_gas_n_bands(const orc_gas*);
 /* Gamma_b and the upper edge (eV) of band b (edge = +inf for the last band). */

@@ -65,13 +65,14 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB_PATH):
+        if not os.path.exists(LIB_PATH) or os.path.getmtime(SRC) > os.path.getmtime(LIB_PATH):
             build()
         L = C.CDLL(LIB_PATH)
         dp, vp, u32p = C.POINTER(C.c_double), C.c_void_p, C.POINTER(C.c_uint32)
         L.orc_gas_create.argtypes = [C.c_double, C.c_int32, C.c_double, C.c_int32,
                                      C.POINTER(_Channel), C.c_int32, C.POINTER(vp)]
         L.orc_gas_destroy.argtypes = [vp]
+        L.orc_gas_set_penning.argtypes = [vp, C.c_int32, C.c_double, C.c_double]
         L.orc_gas_gamma.argtypes = [vp]
         L.orc_gas_gamma.restype = C.c_double
         L.orc_gas_n_bands.argtypes = [vp]
@@ -148,6 +149,12 @@ class Gas:
         if rc:
             raise ValueError(f"orc_gas_create failed ({rc})")
         self.h = h
+        for i, ch in enumerate(gas.channels):
+            p = float(getattr(ch, "penning_prob", 0.0))
+            if p > 0.0:
+                rc = L.orc_gas_set_penning(h, i, p, float(getattr(ch, "penning_energy_eV", 0.0)))
+                if rc:
+                    raise ValueError(f"orc_gas_set_penning failed ({rc})")
         self.n_ch = len(gas.channels)
         self.n_bins = gas.n_bins
 

@@ -41,6 +41,7 @@ SPLIT_UNIFORM, SPLIT_OPAL_BEATY = 0, 1
 VALUES_SIGMA, VALUES_RATE = 0, 1
 
 HARTREE_EV = 27.211386245988  # screening energy of the screened-Rutherford model
+PENNING_QUENCHER_EV = 10.5    # ionisation potential of the synthetic Penning quencher
 GAS_DENSITY = 2.5e19          # cm^-3, ~1 bar at room temperature
 
 
@@ -57,6 +58,8 @@ class Channel:
     mass_ratio: float = 0.0       # elastic: m_e / M
     split_w_eV: float = 0.0       # Opal-Beaty w
     screening_eV: float = 0.0     # screened Rutherford: eta(e) = screening / (8 e)
+    penning_prob: float = 0.0     # excitation: probability of a Penning transfer electron
+    penning_energy_eV: float = 0.0  # excitation: energy of that electron
 
 
 @dataclasses.dataclass
@@ -142,7 +145,8 @@ def toy_gas(e_max_eV: float = 200.0, n_bins: int = 2000, band_bins: int = 0) -> 
 
 
 def argon_like_gas(e_max_eV: float = 400.0, n_bins: int = 20000,
-                   attachment: bool = False, band_bins: int = 0) -> Gas:
+                   attachment: bool = False, band_bins: int = 0,
+                   penning: Optional[float] = None) -> Gas:
     """Synthetic argon-like gas.
 
     * elastic 7e-16*(e/10)^0.5/(1+(0.25/e)^2) cm^2 times a Ramsauer dip
@@ -152,7 +156,11 @@ def argon_like_gas(e_max_eV: float = 400.0, n_bins: int = 20000,
       5e-18*ln(x)/x for x = e/thr > 1;
     * ionisation at 15.7 eV, linear to 3e-16 cm^2 at 100 eV then flat,
       Opal-Beaty split with w = 10 eV;
-    * optionally attachment 1e-18 cm^2 for e < 2 eV.
+    * optionally attachment 1e-18 cm^2 for e < 2 eV;
+    * optionally Penning transfer: every excitation level passes its energy
+      on with probability ``penning`` to a quencher of ionisation potential
+      10.5 eV, freeing an electron of energy thr - 10.5 eV (synthetic: no
+      transfer data are available here).
     """
     e = energy_nodes(e_max_eV, n_bins)
     with np.errstate(divide="ignore", invalid="ignore"):
@@ -166,7 +174,9 @@ def argon_like_gas(e_max_eV: float = 400.0, n_bins: int = 20000,
         x = e / thr
         with np.errstate(divide="ignore", invalid="ignore"):
             s = np.where(x > 1.0, 5e-18 * np.log(x) / x, 0.0)
-        chans.append(Channel(EXCITATION, s, loss_eV=thr, e_lo_eV=thr))
+        chans.append(Channel(EXCITATION, s, loss_eV=thr, e_lo_eV=thr,
+                             penning_prob=0.0 if penning is None else float(penning),
+                             penning_energy_eV=thr - PENNING_QUENCHER_EV))
     ion = np.where(e >= 15.7, 3e-16 * np.minimum((e - 15.7) / (100.0 - 15.7), 1.0), 0.0)
     chans.append(Channel(IONISATION, ion, loss_eV=15.7, e_lo_eV=15.7,
                          split=SPLIT_OPAL_BEATY, split_w_eV=10.0))
@@ -251,7 +261,14 @@ def wire(n_aval: int = 2048, band_bins: int = 0) -> Workload:
                     "argon-like gas, wire counter 25 um / 5 mm / 1500 V polar map, 0.5 T axial B")
 
 
-WORKLOADS = {"toy": toy, "argon": argon, "batched": batched, "highgain": highgain, "wire": wire}
+def penning(n_aval: int = 500, band_bins: int = 0, prob: float = 0.05) -> Workload:
+    return Workload("penning", argon_like_gas(band_bins=band_bins, penning=prob), slab(128e-4, 40e3),
+                    primaries_at_rest(n_aval), n_aval, 6,
+                    f"argon-like gas with Penning transfer p = {prob} (quencher 10.5 eV), 128 um slab, 40 kV/cm")
+
+
+WORKLOADS = {"toy": toy, "argon": argon, "batched": batched, "highgain": highgain, "wire": wire,
+             "penning": penning}
 
 
 def subset_primaries(prim: np.ndarray, modulus: int, residue: int = 0) -> np.ndarray:
