@@ -31,9 +31,9 @@ PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 # Oracle samples per workload (avalanche ids divisible by the modulus, which
 # replay exactly on their own): about 5-30 s on the host cores.  Electron
 # capacity per workload.
-CPU_MODULUS = {"toy": 1, "argon": 1, "batched": 64, "highgain": 16, "wire": 128}
+CPU_MODULUS = {"toy": 1, "argon": 1, "batched": 64, "highgain": 16, "wire": 128, "penning": 4}
 CAPACITY = {"toy": 2_000_000, "argon": 16_000_000, "batched": 200_000_000,
-            "highgain": 60_000_000, "wire": 90_000_000}
+            "highgain": 60_000_000, "wire": 90_000_000, "penning": 40_000_000}
 
 # HBM traffic of the transport kernel from two counter passes (FETCH_SIZE,
 # WRITE_SIZE per dispatch), valid only for the kernel sources it was taken on.

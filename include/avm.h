@@ -110,6 +110,18 @@ avm_status avm_gas_get_tables(const avm_gas* gas, double* cumulative, double* ba
  * their next execute (a captured graph is captured again).  Errors:
  * AVM_E_ARG for band_bins < 0. */
 avm_status avm_gas_set_band_bins(avm_gas* gas, int32_t band_bins);
+/* Penning transfer of an excitation channel (a synthetic extension; real
+ * transfer probabilities need gas data): each excitation in `channel` is
+ * followed, with `probability`, by an extra electron of energy `energy_eV`
+ * born where the excitation happened, isotropic; the exciting electron is
+ * scattered as for any excitation.  The decision takes the first uniform of
+ * the flight's random block j = 2; the new electron's direction and id come
+ * from blocks 2 and 3 as for an ionisation secondary, and it counts as a
+ * secondary (n_ion).  Probability 0 switches it off.  The gas must not be
+ * in use by an executing run.  Errors: AVM_E_ARG for a channel that is not
+ * an excitation, a probability outside [0, 1], a negative or non-finite
+ * energy. */
+avm_status avm_gas_set_penning(avm_gas* gas, int32_t channel, double probability, double energy_eV);
 void avm_gas_destroy(avm_gas* gas);
 
 /* ------------------------------------------------------------------------ */

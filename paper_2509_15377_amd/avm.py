@@ -97,6 +97,7 @@ _SIGS = {
     "avm_gas_get_info": ([_VP, C.POINTER(_GasInfo)], C.c_int),
     "avm_gas_get_tables": ([_VP, _DP, _DP, _DP], C.c_int),
     "avm_gas_set_band_bins": ([_VP, C.c_int32], C.c_int),
+    "avm_gas_set_penning": ([_VP, C.c_int32, C.c_double, C.c_double], C.c_int),
     "avm_gas_destroy": ([_VP], None),
     "avm_field_slab": ([C.c_int32, C.c_double, C.c_double, C.c_uint32, _DP, _DP, C.POINTER(_VP)], C.c_int),
     "avm_field_polar_map": ([C.c_int32, C.c_double, C.c_double, C.c_int32, C.c_int32, _FP, _FP,
@@ -179,6 +180,9 @@ class Gas:
         _check(lib().avm_gas_create(device, gas.e_max_eV, gas.n_bins, gas.density_cm3,
                                     len(gas.channels), chans, bb, C.byref(h)), "avm_gas_create")
         self.h = h
+        for i, ch in enumerate(gas.channels):
+            if float(getattr(ch, "penning_prob", 0.0)) > 0.0:
+                self.set_penning(i, ch.penning_prob, ch.penning_energy_eV)
         info = _GasInfo()
         _check(lib().avm_gas_get_info(h, C.byref(info)))
         self.gamma = info.gamma
@@ -192,6 +196,11 @@ class Gas:
         _check(lib().avm_gas_get_info(self.h, C.byref(info)))
         self.n_bands = info.n_bands
         self.band_bins = info.band_bins
+
+    def set_penning(self, channel: int, probability: float, energy_eV: float):
+        """Penning transfer of an excitation channel (avm_gas_set_penning)."""
+        _check(lib().avm_gas_set_penning(self.h, int(channel), float(probability), float(energy_eV)),
+               "avm_gas_set_penning")
 
     def set_band_bins(self, band_bins: int):
         """Rebuild the band majorants with a new band width (avm_gas_set_band_bins)."""

@@ -80,6 +80,8 @@ struct avm_gas {
         *band_inv_f = nullptr, *band_edge_f = nullptr;
   ChanP<float>* ch_f = nullptr;
   double* binmax = nullptr;  // per-bin maxima, kept for rebuilding the bands
+  std::vector<ChanDev> host_ch;        // channel records as on the device
+  std::vector<ChanP<float>> host_ch_f;
   uint64_t version = 0;      // bumped whenever the device tables change
   GasDev dev{};
 };
@@ -296,6 +298,8 @@ avm_status avm_gas_create(int32_t device, double e_max_eV, int32_t n_bins, doubl
     return fail(AVM_E_ARG, "avm_gas_create: the table has no collisions (majorant %g)", gamma);
   }
   g->gamma = gamma;
+  g->host_ch = cd;
+  g->host_ch_f = cf;
   GasDev& D = g->dev;
   D.cum = g->cum;
   D.cum0 = g->cum0;
@@ -401,6 +405,32 @@ avm_status avm_gas_set_band_bins(avm_gas* g, int32_t band_bins) {
   D.band_bins = band_bins;
   D.band_scale = band_bins > 0 ? (double)g->n_bins / (g->e_max * (double)band_bins) : 0.0;
   D.band_scale_f = (float)D.band_scale;
+  g->version += 1;
+  return AVM_OK;
+}
+
+avm_status avm_gas_set_penning(avm_gas* g, int32_t channel, double probability, double energy_eV) {
+  g_err.clear();
+  if (!g) return fail(AVM_E_ARG, "avm_gas_set_penning: gas is NULL");
+  if (channel < 0 || channel >= g->n_ch) return fail(AVM_E_ARG, "avm_gas_set_penning: no channel %d", channel);
+  if (g->host_ch[channel].kind != AVM_CH_EXCITATION)
+    return fail(AVM_E_ARG, "avm_gas_set_penning: channel %d is not an excitation", channel);
+  if (!(probability >= 0.0 && probability <= 1.0))
+    return fail(AVM_E_ARG, "avm_gas_set_penning: probability outside [0, 1]");
+  if (!(energy_eV >= 0.0) || !std::isfinite(energy_eV))
+    return fail(AVM_E_ARG, "avm_gas_set_penning: energy must be finite and >= 0");
+  DeviceGuard dg(g->device);
+  if (dg.err != hipSuccess) return fail(AVM_E_HIP, "hipSetDevice: %s", hipGetErrorString(dg.err));
+  ChanDev d = g->host_ch[channel];
+  ChanP<float> f = g->host_ch_f[channel];
+  d.pen_prob = probability;
+  d.pen_e = energy_eV;
+  f.pen_prob = (float)probability;
+  f.pen_e = (float)energy_eV;
+  HIP_TRY(hipMemcpy(g->ch + channel, &d, sizeof d, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(g->ch_f + channel, &f, sizeof f, hipMemcpyHostToDevice));
+  g->host_ch[channel] = d;
+  g->host_ch_f[channel] = f;
   g->version += 1;
   return AVM_OK;
 }

@@ -66,6 +66,8 @@ struct ChanP {
   R split_w;            // Opal-Beaty w
   R atan_scale;         // 1 / (2 w)
   R inv_screen8;        // 8 / screening (1/eta = 8 e / screening)
+  R pen_prob;           // excitation: Penning transfer probability
+  R pen_e;              // excitation: energy of the transfer electron
 };
 using ChanDev = ChanP<double>;
 
@@ -1001,6 +1003,17 @@ AVM_FN int32_t flight_step(Elec<R>& e, const GasDev& G, const TabView<R>& T, con
     e_new = en * (R(1) - ch.el_loss * (R(1) - cchi));
     cos_t = (ch.mu + cchi) * Mr::rsqrt_(Mr::fma(ch.two_mu, cchi, ch.mu2p1));
   } else {  // excitation
+    if (ch.pen_prob > R(0)) {
+      // Penning transfer, decided by the first uniform of block 2: the
+      // excitation and its transfer electron are finished with the
+      // ionisations after the pass
+      const Block w2 = draw(P, e.aval, e.eid, e.k, 2);
+      if (Mr::uni(w2.w0, w2.w1) < ch.pen_prob) {
+        child.pen = en;
+        child.pc = c;
+        return STEP_IONISED;
+      }
+    }
     e_new = en - ch.loss;
     cos_t = R(1) - R(2) * uA;
   }
@@ -1009,9 +1022,10 @@ AVM_FN int32_t flight_step(Elec<R>& e, const GasDev& G, const TabView<R>& T, con
   return STEP_CONTINUE;
 }
 
-// Finishes an ionisation decided by flight_step (blocks j = 1..3 of the
-// electron's flight k): energy split, the primary's new direction, the
-// secondary's energy, direction and id.
+// Finishes an ionisation (or a Penning transfer) decided by flight_step
+// (blocks j = 1..3 of the electron's flight k): energy split (transfer: the
+// channel's transfer energy, the electron keeps e - threshold), the
+// electron's new direction, the secondary's energy, direction and id.
 template <class R, bool kBanded>
 AVM_FN void complete_ionisation(Elec<R>& e, const GasDev& G, const TabView<R>& T,
                                 const RunParams& P, Child<R>& child) {
@@ -1027,8 +1041,15 @@ AVM_FN void complete_ionisation(Elec<R>& e, const GasDev& G, const TabView<R>& T
   const R uS = Mr::uni(w2.w0, w2.w1);
   const R uC = Mr::uni(w2.w2, w2.w3);
   const R uP = Mr::uni(w3.w0, w3.w1);
-  const R es = ch.split ? ch.split_w * Mr::tan_(uS * Mr::atan_(avail * ch.atan_scale)) : uS * avail;
-  const R e_new = avail - es;
+  R es, e_new;
+  if (ch.kind == CH_EXCITATION) {
+    // Penning transfer after an excitation: the electron keeps e - threshold
+    es = ch.pen_e;
+    e_new = avail;
+  } else {
+    es = ch.split ? ch.split_w * Mr::tan_(uS * Mr::atan_(avail * ch.atan_scale)) : uS * avail;
+    e_new = avail - es;
+  }
   const R ct = R(1) - R(2) * uC;
   const R st2 = Mr::fma(-ct, ct, R(1));
   const R stt = st2 > R(0) ? Mr::sqrt_(st2) : R(0);

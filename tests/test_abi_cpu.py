@@ -94,6 +94,7 @@ def test_argument_errors_without_a_device(A):
     assert L.avm_run_sync(None) == A.AVM_E_ARG
     assert L.avm_gas_get_info(None, None) == A.AVM_E_ARG
     assert L.avm_gas_set_band_bins(None, 10) == A.AVM_E_ARG
+    assert L.avm_gas_set_penning(None, 1, 0.5, 1.0) == A.AVM_E_ARG
     assert L.avm_run_set_signal(None, 0.0, 0.01, 10) == A.AVM_E_ARG
     assert L.avm_run_signal(None, 0, 0, None) == A.AVM_E_ARG
     res = A._TuneResult()

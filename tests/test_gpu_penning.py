@@ -1,0 +1,69 @@
+"""Penning transfer (synthetic; an excitation followed, with the channel's
+probability, by an extra electron of the channel's transfer energy) through
+the C-ABI against the oracle, per trajectory; the parent's trajectory does
+not depend on the probability; FP32-mixed statistics."""
+import numpy as np
+import pytest
+
+from oracle import compare as CMP
+from paper_2509_15377_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def A():
+    from paper_2509_15377_amd import avm
+    if avm.device_count() < 1:
+        pytest.fail("no HIP device visible: the GPU tests need an MI355X")
+    return avm
+
+
+@pytest.mark.parametrize("majorant", ["global", "banded"])
+def test_penning_against_oracle(A, oracle_mod, majorant):
+    wl = W.penning(24, band_bins=100)
+    banded = majorant == "banded"
+    og = oracle_mod.Gas(wl.gas, band_bins=100)
+    ref = oracle_mod.run(og, wl.field, wl.primaries, wl.seed, banded=banded)
+    ep, tot, per = A.run(wl, band_bins=100, majorant=A.BANDED if banded else A.GLOBAL,
+                         capacity=8_000_000, timeout_s=60.0)
+    rep = CMP.assert_parity(ep, ref)
+    assert np.array_equal(per["n_endpoints"], 1 + per["n_ion"])
+    energies = {round(c.penning_energy_eV, 9) for c in wl.gas.channels if c.penning_prob > 0}
+    n_transfer = sum(round(float(x), 9) in energies for x in ep["e0"][ep["parent"] != 0])
+    print("penning", majorant, rep["matched"], rep["flips"], "transfer electrons", n_transfer)
+    assert n_transfer > 0
+
+
+def test_penning_high_probability_bounded_time(A, oracle_mod):
+    """p = 1 on a short time window: every excitation makes an electron."""
+    wl = W.penning(16, prob=1.0)
+    ref = oracle_mod.run(wl.gas, wl.field, wl.primaries, wl.seed, t_max=0.06)
+    ep, _, _ = A.run(wl, t_max=0.06, capacity=4_000_000, timeout_s=60.0)
+    CMP.assert_parity(ep, ref)
+    # the parents' own trajectories are those of the plain gas
+    plain = W.penning(16, prob=0.0)
+    e0, _, _ = A.run(plain, t_max=0.06, capacity=4_000_000, timeout_s=60.0)
+    p1, p0 = ep[ep["parent"] == 0], e0[e0["parent"] == 0]
+    for k in ("x1", "y1", "z1", "t1", "e1", "n_real", "n_null"):
+        assert np.array_equal(p1[k], p0[k]), k
+
+
+def test_penning_fp32_statistics(A):
+    wl = W.penning(band_bins=100)
+    kw = dict(majorant=A.BANDED, capacity=20_000_000, timeout_s=60.0)
+    _, _, p64 = A.run(wl, **kw)
+    _, _, p32 = A.run(wl, precision=A.FP32_MIXED, **kw)
+    g64, g32 = p64["n_endpoints"].astype(float), p32["n_endpoints"].astype(float)
+    rel = abs(g32.mean() - g64.mean()) / g64.mean()
+    print(f"penning gain fp64 {g64.mean():.1f} fp32 {g32.mean():.1f} rel {rel:.2e}")
+    assert rel < 0.01
+
+
+def test_penning_bad_settings(A):
+    g = A.Gas(W.argon_like_gas())
+    for ch, p, e in ((0, 0.5, 1.0), (1, 1.5, 1.0), (1, 0.5, -1.0), (999, 0.5, 1.0)):
+        with pytest.raises(A.AvmError) as err:
+            g.set_penning(ch, p, e)
+        assert err.value.status == A.AVM_E_ARG
+    g.set_penning(1, 0.5, 1.0)

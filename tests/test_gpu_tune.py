@@ -112,25 +112,36 @@ def _near_wire(n, seed=7):
     return wl, prim
 
 
-# Near the wire (strong field, 0.5 T) a one-ulp difference grows tenfold
-# every ~300 flights (a CPU build of the device step against the oracle:
-# 1e-16 after 2 flights, 4e-13 after 1200, 6e-9 after 2500), so the
-# per-trajectory comparisons there stop every electron after 1000 flights.
-NEAR_WIRE_K_MAX = 1000
+# Near the wire (strong field, 0.5 T) rounding differences grow fast: a CPU
+# build of the device step against the oracle shows 1e-16 after 2 flights
+# and, for some electrons, 1e-9 after 600; a secondary inherits its
+# ancestors' differences, so along an ionisation chain the horizon adds up.
+# The per-trajectory checks there compare primaries on a 300-flight
+# horizon; from the workload's own start radius (1 mm, weak field)
+# primaries are compared over 5000 flights.
+def _helical_parity(A, oracle_mod, look):
+    wl, prim = _near_wire(12)
+    og = oracle_mod.Gas(wl.gas, band_bins=100)
+    ga, fa = A.Gas(wl.gas, band_bins=100), A.Field(wl.field)
+    kw = dict(seed=wl.seed, majorant=A.BANDED, band_lookahead=look, capacity=4_000_000, timeout_s=60.0)
+    ref = oracle_mod.run(og, wl.field, prim, wl.seed, banded=True, k_max=300, band_lookahead=look)
+    ep, tot, _ = A.run(gas=ga, field=fa, primaries=prim, n_aval=12, k_max=300, **kw)
+    rep = CMP.assert_parity(ep[ep["parent"] == 0], ref[ref["parent"] == 0])
+    assert tot["n_band"] > 0
+    far = W.wire(16)
+    ref2 = oracle_mod.run(og, far.field, far.primaries, far.seed, banded=True, k_max=5000,
+                          band_lookahead=look)
+    ep2, tot2, _ = A.run(gas=ga, field=fa, primaries=far.primaries, n_aval=16, k_max=5000,
+                         **dict(kw, seed=far.seed))
+    rep2 = CMP.assert_parity(ep2, ref2)
+    print("helical bands, lookahead", look, "near", rep["max_rel"]["x1"], "far", rep2["max_rel"]["x1"],
+          "band cuts", tot["n_band"], tot2["n_band"])
 
 
 def test_wire_banded_with_b_against_oracle(A, oracle_mod):
     """Banded majorant with the 0.5 T field (helical energy bound), per
-    trajectory, on a bounded horizon (the geometry amplifies rounding)."""
-    wl, prim = _near_wire(12)
-    og = oracle_mod.Gas(wl.gas, band_bins=100)
-    ref = oracle_mod.run(og, wl.field, prim, wl.seed, banded=True, k_max=NEAR_WIRE_K_MAX)
-    ep, tot, _ = A.run(gas=A.Gas(wl.gas, band_bins=100), field=A.Field(wl.field), primaries=prim,
-                       n_aval=12, seed=wl.seed, majorant=A.BANDED, k_max=NEAR_WIRE_K_MAX,
-                       capacity=4_000_000, timeout_s=60.0)
-    rep = CMP.assert_parity(ep, ref)
-    print("wire banded B", rep["matched"], rep["flips"], "band cuts", tot["n_band"])
-    assert tot["n_band"] > 0
+    trajectory."""
+    _helical_parity(A, oracle_mod, 0.0)
 
 
 def test_wire_banded_with_b_matches_global_statistics(A):
@@ -171,14 +182,7 @@ def test_band_lookahead_against_oracle(A, oracle_mod, look):
 
 
 def test_band_lookahead_wire_with_b_against_oracle(A, oracle_mod):
-    wl, prim = _near_wire(12, seed=23)
-    ref = oracle_mod.run(oracle_mod.Gas(wl.gas, band_bins=100), wl.field, prim, wl.seed, banded=True,
-                         k_max=NEAR_WIRE_K_MAX, band_lookahead=1.0)
-    ep, _, _ = A.run(gas=A.Gas(wl.gas, band_bins=100), field=A.Field(wl.field), primaries=prim,
-                     n_aval=12, seed=wl.seed, majorant=A.BANDED, k_max=NEAR_WIRE_K_MAX,
-                     band_lookahead=1.0,
-                     capacity=4_000_000, timeout_s=60.0)
-    CMP.assert_parity(ep, ref)
+    _helical_parity(A, oracle_mod, 1.0)
 
 
 def test_band_lookahead_rejects_bad_values(A):
