@@ -31,6 +31,10 @@ PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 # Oracle samples per workload (avalanche ids divisible by the modulus, which
 # replay exactly on their own): about 5-30 s on the host cores.  Electron
 # capacity per workload.
+# Band lookahead of the banded majorant (mean free times), headline and
+# CPU baseline alike.
+BAND_LOOKAHEAD = 1.0
+
 CPU_MODULUS = {"toy": 1, "argon": 1, "batched": 64, "highgain": 16, "wire": 128, "penning": 4}
 CAPACITY = {"toy": 2_000_000, "argon": 16_000_000, "batched": 200_000_000,
             "highgain": 60_000_000, "wire": 90_000_000, "penning": 40_000_000}
@@ -96,7 +100,8 @@ def side_legs(args, make, timed, paths, gas, field, wl, capacity, stream):
         "null_fraction": (gc["n_null"] + gc["n_masked"]) / max(gfl, 1)}
     gr.close()
     hr = avm.Run(gas, field, wl.primaries, wl.n_aval, seed=wl.seed, majorant=avm.BANDED,
-                 mode=avm.BATCHED, capacity=capacity, timeout_s=300.0, stream=stream)
+                 mode=avm.BATCHED, capacity=capacity, timeout_s=300.0, stream=stream,
+                 band_lookahead=BAND_LOOKAHEAD)
     hw, _ = timed(hr)
     hms = hw * 1e3 / args.steps
     paths["batched_fp64_banded_host_primaries"] = {
@@ -134,7 +139,7 @@ def crossover():
     for n in (1, 2, 4, 8, 16, 32, 64, 128, 256, 512, 1024):
         prim = full.primaries[:n]
         r = avm.Run(gas, field, prim, n, seed=full.seed, majorant=avm.BANDED, capacity=20_000_000,
-                    timeout_s=120.0)
+                    timeout_s=120.0, band_lookahead=BAND_LOOKAHEAD)
         r.execute()
         r.sync()
         torch.cuda.synchronize()
@@ -147,7 +152,7 @@ def crossover():
         electrons = r.counts()["n_endpoints"]
         r.close()
         t1 = time.perf_counter()
-        O.run(og, of, prim, full.seed, banded=True)
+        O.run(og, of, prim, full.seed, banded=True, band_lookahead=BAND_LOOKAHEAD)
         tc = time.perf_counter() - t1
         rows.append({"avalanches": n, "electrons": int(electrons), "gpu_s": float(np.median(ts)),
                      "oracle_s": tc})
@@ -211,7 +216,8 @@ def main():
     def make(mode, majorant, precision=avm.FP64, graph=False):
         return avm.Run(gas, field, prim_dev, wl.n_aval, seed=wl.seed, precision=precision,
                        majorant=majorant, mode=mode, capacity=capacity, timeout_s=300.0,
-                       stream=stream, graph=graph)
+                       stream=stream, graph=graph,
+                       band_lookahead=BAND_LOOKAHEAD if majorant == avm.BANDED else 0.0)
 
     def timed(run):
         for _ in range(args.warmup):
@@ -286,11 +292,12 @@ def main():
         sel = W.subset_primaries(wl.primaries, mod)
         t2 = time.perf_counter()
         ep, threads = O.run(og, of, wl.primaries[sel], wl.seed, banded=True, ids=sel,
-                            return_threads=True)
+                            return_threads=True, band_lookahead=BAND_LOOKAHEAD)
         tc = time.perf_counter() - t2
         idx = W.subset_primaries(wl.primaries, 20 * mod)
         t3 = time.perf_counter()
-        ep1 = O.run(og, of, wl.primaries[idx], wl.seed, banded=True, ids=idx, threads=1)
+        ep1 = O.run(og, of, wl.primaries[idx], wl.seed, banded=True, ids=idx, threads=1,
+                    band_lookahead=BAND_LOOKAHEAD)
         t1c = time.perf_counter() - t3
         cpu = {"value": float(ep["n_real"].sum() / tc), "unit": "real collisions/s",
                "cores": int(threads), "kind": "oracle",
@@ -316,7 +323,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{wl.name}: {wl.description}", "avalanches": wl.n_aval,
                    "electrons_per_step": c["n_endpoints"], "mean_gain": c["n_endpoints"] / wl.n_aval,
-                   "path": "batched persistent kernel, banded majorant (100 bins/band), FP64",
+                   "path": "batched persistent kernel, banded majorant (100 bins/band, "
+                           f"lookahead {BAND_LOOKAHEAD:g} mean free time), FP64, graph replay",
                    "seed": wl.seed},
         "secondaries_per_s": c["n_ion"] / (ms_step * 1e-3),
         "flights_per_s": flights / (ms_step * 1e-3),

@@ -128,15 +128,16 @@ def test_wire_polar_map_with_b(A, oracle_mod):
 
 def test_full_argon_bench_configuration_sampled(A, oracle_mod):
     """The benchmark's launch configuration (1000 avalanches, batched,
-    banded, FP64) checked on every 50th avalanche, which the oracle replays
-    exactly on its own."""
+    banded with lookahead 1, FP64, graph replay) checked on every 50th
+    avalanche, which the oracle replays exactly on its own."""
     wl = W.argon(band_bins=100)
-    ep, tot, per = A.run(wl, majorant=A.BANDED, capacity=8_000_000)
+    ep, tot, per = A.run(wl, majorant=A.BANDED, capacity=8_000_000, band_lookahead=1.0, graph=True)
     assert tot["n_endpoints"] == wl.n_aval + tot["n_ion"]
     assert np.array_equal(per["n_endpoints"], 1 + per["n_ion"])
     idx = W.subset_primaries(wl.primaries, 50)
     g = oracle_mod.Gas(wl.gas)
-    ref = oracle_mod.run(g, wl.field, wl.primaries[idx], wl.seed, banded=True, ids=idx)
+    ref = oracle_mod.run(g, wl.field, wl.primaries[idx], wl.seed, banded=True, ids=idx,
+                         band_lookahead=1.0)
     sub = ep[(ep["aval"] % 50) == 0]
     rep = CMP.assert_parity(sub, ref)
     print("argon full sampled", rep, "electrons", tot["n_endpoints"])

@@ -60,21 +60,22 @@ def test_signal_wire_with_b_against_oracle(A, oracle_mod):
 
 
 def test_signal_full_size_sum_rule_and_sample(A, oracle_mod):
-    """The benchmark configuration (1000 avalanches, banded, FP64) with the
-    signal on: per avalanche the bins add up to the sum of (z1 - z0)/d over
-    its endpoints (a property at any size), and every 100th avalanche
-    matches the oracle's replay bin by bin."""
+    """The benchmark configuration (1000 avalanches, banded with lookahead 1,
+    FP64) with the signal on: per avalanche the bins add up to the sum of
+    (z1 - z0)/d over its endpoints (a property at any size), and every 100th
+    avalanche matches the oracle's replay bin by bin."""
     wl = W.argon(band_bins=100)
     spec = (0.0, 0.005, 240)
     ep, tot, per, sig = A.run(wl, majorant=A.BANDED, capacity=8_000_000, signal=spec,
-                              timeout_s=60.0)
+                              timeout_s=60.0, band_lookahead=1.0)
     assert ep["t1"].max() < spec[0] + spec[1] * spec[2]
     d = wl.field.z_hi_cm - wl.field.z_lo_cm
     expect = np.bincount(ep["aval"], weights=(ep["z1"] - ep["z0"]) / d, minlength=wl.n_aval)
     assert np.allclose(sig.sum(axis=1), expect, rtol=1e-10, atol=1e-10)
     idx = W.subset_primaries(wl.primaries, 100)
     _, ref_sig = oracle_mod.run(oracle_mod.Gas(wl.gas, band_bins=100), wl.field, wl.primaries[idx],
-                                wl.seed, banded=True, ids=idx, signal=spec + (wl.n_aval,))
+                                wl.seed, banded=True, ids=idx, signal=spec + (wl.n_aval,),
+                                band_lookahead=1.0)
     print("full-size sample max rel", _close(sig[idx], ref_sig[idx]))
 
 
