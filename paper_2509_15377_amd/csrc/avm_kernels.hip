@@ -340,6 +340,15 @@ struct Xfer {
   uint32_t slot[64], aval[64];
 };
 
+// Back-off of a wave with no electron: repeated s_sleep(AVM_IDLE_NAP)
+// (64 cycles each per unit), up to AVM_IDLE_MAX_NAPS in a row.
+#ifndef AVM_IDLE_NAP
+#define AVM_IDLE_NAP 2
+#endif
+#ifndef AVM_IDLE_MAX_NAPS
+#define AVM_IDLE_MAX_NAPS 1
+#endif
+
 // Occupancy target of the persistent kernel (waves per SIMD); the register
 // budget follows from it.
 #ifndef AVM_PERSISTENT_WAVES_PER_EU
@@ -403,6 +412,7 @@ __global__ void __launch_bounds__(kPBlock)
   Xfer& X = xfer_all[threadIdx.x >> 6];
   const uint32_t lane = __lane_id();
   bool has = false, done = false, cp = false;
+  int idle_naps = 0;  // a wave with no electron backs off, longer the longer it stays idle
   unsigned long long claim = kNone;
   uint32_t slot = 0;
   Elec<R> e;
@@ -544,7 +554,15 @@ __global__ void __launch_bounds__(kPBlock)
     }
     if (!has && !done && ld_coh_int(&ctr->live) == 0) done = true;
     if (__ballot(!done) == 0) break;
-    if (__ballot(has) == 0) __builtin_amdgcn_s_sleep(2);
+    if (__ballot(has) == 0) {
+      // nothing to carry: leave the SIMD to busy waves for a while before
+      // polling the queue again (the polls and the exchange code would
+      // otherwise take their issue slots)
+      idle_naps = idle_naps < AVM_IDLE_MAX_NAPS ? 2 * idle_naps + 1 : AVM_IDLE_MAX_NAPS;
+      for (int i = 0; i < idle_naps; ++i) __builtin_amdgcn_s_sleep(AVM_IDLE_NAP);
+    } else {
+      idle_naps = 0;
+    }
   }
 }
 
