@@ -26,16 +26,18 @@ struct Store {
   uint64_t capacity;
 };
 
-// Device counters of a run.
+// Device counters of a run.  The ones every wave of the persistent kernel
+// updates or polls sit on separate 256-byte blocks: device-scope atomics are
+// performed at the memory side, and counters sharing a line serialise there.
 struct Counters {
-  unsigned long long tail;     // slots requested (electrons created, incl. dropped)
-  unsigned long long qhead;    // batched: queue entries claimed by lanes
-  unsigned long long live;     // batched: electrons created and not yet terminated
-  unsigned long long next;     // plain: size of the next active list
-  unsigned long long err;      // bad primary avalanche id
-  unsigned long long timeout;  // a transport kernel ran out of its time budget
-  unsigned long long qtail;    // batched: queue entries published or being published
-  unsigned long long epoch;    // run counter (bumped by every reset; tags queue entries)
+  alignas(256) unsigned long long tail;   // slots requested (electrons created, incl. dropped)
+  alignas(256) unsigned long long qhead;  // batched: queue entries claimed by lanes
+  alignas(256) unsigned long long qtail;  // batched: queue entries published or being published
+  alignas(256) unsigned long long ended;  // batched: electrons terminated or dropped, as flushed by waves
+  alignas(256) unsigned long long next;   // plain: size of the next active list
+  unsigned long long err;                 // bad primary avalanche id
+  unsigned long long timeout;             // a transport kernel ran out of its time budget
+  unsigned long long epoch;               // run counter (bumped by every reset; tags queue entries)
 };
 
 // Per-avalanche statistics (and totals, with the status histogram).

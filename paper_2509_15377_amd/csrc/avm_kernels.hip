@@ -132,7 +132,7 @@ __global__ void k_reset(Counters* ctr, uint64_t n_prim, AvalStats* stats, uint32
     ctr->tail = n_prim;
     ctr->qhead = 0;
     ctr->qtail = n_prim;
-    ctr->live = n_prim;
+    ctr->ended = 0;
     ctr->next = 0;
     ctr->err = 0;
     ctr->timeout = 0;
@@ -362,17 +362,23 @@ struct Xfer {
 // flights; a lane stops early when its electron ends or ionises (the
 // secondary waits in registers).  At the end of a pass the wave, in
 // lockstep:
-//   1. allocates storage slots for its new secondaries (one atomic);
+//   1. allocates storage slots for its new secondaries (one atomic on
+//      `tail`, which so counts every electron created, before any of them
+//      can be seen by another wave);
 //   2. hands secondaries to its own idle lanes through LDS (ballot/mbcnt
 //      ranks: the k-th secondary goes to the k-th idle lane);
 //   3. publishes the remaining secondaries on the global queue (one atomic
 //      on qtail; records written device-coherent, then the entry's ready
 //      word after the record stores are acknowledged);
-//   4. updates `live` (electrons in existence) once with its net change;
+//   4. counts its terminated (and dropped) electrons locally;
 //   5. lets its still-idle lanes claim queue entries (one atomic on qhead)
 //      and picks up entries whose ready word shows the run's epoch.
-// A lane leaves when it is idle with no usable claim and live == 0: then no
-// electron exists anywhere and none can appear.
+// A wave that holds no electron adds its local count to `ended` (one
+// atomic), so `ended` never exceeds the number of electrons terminated.
+// Reading `ended` and then `tail` and finding them equal means every
+// electron created by the first read had terminated by then, and none was
+// created in between: no electron exists and none can appear, and the wave
+// leaves.
 //
 // kSignal: the electrons also deposit their induced signal (Shockley-Ramo,
 // binned in time) on the readout electrode.
@@ -414,7 +420,8 @@ __global__ void __launch_bounds__(kPBlock)
   }
   Xfer& X = xfer_all[threadIdx.x >> 6];
   const uint32_t lane = __lane_id();
-  bool has = false, done = false, cp = false;
+  bool has = false, cp = false;
+  unsigned long long n_gone = 0;  // electrons this wave terminated or dropped, not yet in `ended`
   int idle_naps = 0;  // a wave with no electron backs off, longer the longer it stays idle
   unsigned long long claim = kNone;
   uint32_t slot = 0;
@@ -429,7 +436,7 @@ __global__ void __launch_bounds__(kPBlock)
       break;
     }
     // ---- transport pass
-    uint32_t ended = 0;
+    uint32_t term = 0;  // this lane's electron terminated in this pass
     for (int f = 0; f < flights_per_pass && has && !cp; ++f) {
       uint32_t status = 0;
       const int32_t r = flight_step<R, kBanded, kField, kSignal>(e, G, T, F, P, child, status, &Q);
@@ -439,7 +446,7 @@ __global__ void __launch_bounds__(kPBlock)
         if (kSignal) signal_end<R, kField>(Q, e);
         write_end<R>(pinned(Sg), slot, e, P, status);
         has = false;
-        ended = 1;
+        term = 1;
       }
     }
     // ---- ionisations of this pass, finished together
@@ -455,7 +462,9 @@ __global__ void __launch_bounds__(kPBlock)
     const unsigned long long cs = wave_alloc(&ctr->tail, cp);
     const bool stored = cp && cs < S.capacity;
     const uint64_t m_child = __ballot(stored);
-    const uint64_t m_idle = __ballot(!has && !done && claim == kNone);
+    // 4. terminations and dropped secondaries of this pass
+    n_gone += __popcll(__ballot(term != 0)) + __popcll(__ballot(cp && !stored));
+    const uint64_t m_idle = __ballot(!has && claim == kNone);
     const uint32_t n_child = __popcll(m_child), n_idle = __popcll(m_idle);
     const uint32_t n_match = n_child < n_idle ? n_child : n_idle;
     const uint32_t rank_c = __builtin_amdgcn_mbcnt_hi((uint32_t)(m_child >> 32),
@@ -508,16 +517,9 @@ __global__ void __launch_bounds__(kPBlock)
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    // 4. net change of the number of electrons in existence
-    {
-      const int delta = (int)n_child - (int)__popcll(__ballot(ended != 0));
-      if (delta != 0 && lane == (uint32_t)__builtin_ctzll(__ballot(1)))
-        __hip_atomic_fetch_add(&ctr->live, (unsigned long long)(long long)delta, __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-    }
     cp = false;
     // 5. still-idle lanes claim queue entries while the queue has some
-    const bool want = !has && !done && claim == kNone && !take;
+    const bool want = !has && claim == kNone && !take;
     const uint64_t m_want = __ballot(want);
     if (m_want) {
       const unsigned long long qt = ld_coh_int(&ctr->qtail);
@@ -540,7 +542,7 @@ __global__ void __launch_bounds__(kPBlock)
       load_elec_tail<R, kBanded, kField>(G, T, F, P, e);
       if (kSignal) signal_birth<R, kField>(Q, e);
       has = true;
-    } else if (!has && !done && claim != kNone) {
+    } else if (!has && claim != kNone) {
       if (claim < S.capacity && ld_coh_int(&S.qready[claim]) == epoch) {
         slot = ld_coh_int(&S.qslot[claim]);
         e.x = ld_coh(&S.x0[slot]); e.y = ld_coh(&S.y0[slot]); e.z = ld_coh(&S.z0[slot]);
@@ -555,8 +557,22 @@ __global__ void __launch_bounds__(kPBlock)
         claim = kNone;
       }
     }
-    if (!has && !done && ld_coh_int(&ctr->live) == 0) done = true;
-    if (__ballot(!done) == 0) break;
+    if (__ballot(has) == 0) {
+      // no electron in this wave: flush the local count, then test for the
+      // end.  (A pending claim is no electron: below qtail its entry is
+      // counted in `tail` and not ended; at or beyond qtail -- lanes may
+      // claim past it, reading qtail and qhead apart from the claim -- it
+      // names an entry that does not exist yet.)
+      if (n_gone != 0) {
+        if (lane == (uint32_t)__builtin_ctzll(__ballot(1)))
+          __hip_atomic_fetch_add(&ctr->ended, n_gone, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        n_gone = 0;
+      }
+      // `tail` is read after `ended` has arrived: its address depends on the
+      // value read (n_end < 2^63, so the offset is zero)
+      const unsigned long long n_end = ld_coh_int(&ctr->ended);
+      if (n_end == ld_coh_int(&ctr->tail + (n_end >> 63))) break;
+    }
     if (__ballot(has) == 0) {
       // nothing to carry: leave the SIMD to busy waves for a while before
       // polling the queue again (the polls and the exchange code would
