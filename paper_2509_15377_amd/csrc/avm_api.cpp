@@ -652,7 +652,7 @@ avm_status avm_run_create(const avm_gas* gas, const avm_field* field, const avm_
   if (o.capacity == 0) o.capacity = n_prim * 64 > (1u << 20) ? n_prim * 64 : (1u << 20);
   if (o.capacity < n_prim) return fail(AVM_E_ARG, "avm_run_create: capacity %llu < %llu primaries", (unsigned long long)o.capacity, (unsigned long long)n_prim);
   if (o.capacity > 0xFFFFFFF0ull) return fail(AVM_E_ARG, "avm_run_create: capacity above 2^32-16");
-  if (o.flights_per_pass <= 0) o.flights_per_pass = 64;
+  if (o.flights_per_pass <= 0) o.flights_per_pass = 32;
   if (o.waves_per_cu < 0) return fail(AVM_E_ARG, "avm_run_create: waves_per_cu < 0");
   if (!(o.band_lookahead >= 0.0f) || !std::isfinite(o.band_lookahead))
     return fail(AVM_E_ARG, "avm_run_create: band_lookahead must be finite and >= 0");
@@ -1153,7 +1153,7 @@ extern "C" avm_status avm_autotune(avm_gas* gas, const avm_field* field, const a
   std::memset(out, 0, sizeof *out);
   avm_run_opts o = *base;
   o.graph = 0;
-  if (o.flights_per_pass <= 0) o.flights_per_pass = 64;  // the run's default
+  if (o.flights_per_pass <= 0) o.flights_per_pass = 32;  // the run's default
   const bool tune_bands = (flags & AVM_TUNE_BANDS) && o.majorant == AVM_MAJORANT_BANDED && !field->dev.has_b;
   const int32_t bb0 = gas->band_bins;
   DeviceGuard dg(gas->device);
