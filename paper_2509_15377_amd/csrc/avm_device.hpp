@@ -205,6 +205,7 @@ AVM_FN Block draw(const RunParams& p, uint32_t aval, uint64_t eid, uint32_t k, u
   return philox(4u * k + j, aval, (uint32_t)eid, (uint32_t)(eid >> 32), p.key0, p.key1);
 }
 
+
 // 53-bit uniform in (0, 1]: ((hi >> 5) 2^26 + (lo >> 6) + 1) 2^-53, every
 // intermediate an exact integer in binary64.
 AVM_FN double u53(uint32_t hi, uint32_t lo) {
@@ -248,6 +249,29 @@ AVM_FN double rcp_seed(double d) {
   return __builtin_amdgcn_rcp(d);
 #else
   return 1.0 / d;
+#endif
+}
+
+// Square root of x >= 0 (0 for x <= 0) in the range the loop uses: the
+// hardware reciprocal square root refined by one coupled Goldschmidt step
+// and two Newton corrections of the root (Markstein's scheme).  Correctly
+// rounded: no difference from the IEEE square root on 1e8 arguments over
+// 1e-12..1e2, even from a seed with 3e-5 relative error; it skips the
+// rescaling and special-value handling of the general routine.
+AVM_FN double sqrt_nn(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  const double y = __builtin_amdgcn_rsq(x);
+  double g = x * y, h = 0.5 * y;
+  const double r = __builtin_fma(-g, h, 0.5);
+  g = __builtin_fma(g, r, g);
+  h = __builtin_fma(h, r, h);
+  double d = __builtin_fma(-g, g, x);
+  g = __builtin_fma(d, h, g);
+  d = __builtin_fma(-g, g, x);
+  g = __builtin_fma(d, h, g);
+  return x > 0.0 ? g : 0.0;
+#else
+  return x > 0.0 ? sqrt(x) : 0.0;
 #endif
 }
 
@@ -337,7 +361,7 @@ template <class R> struct M;
 template <> struct M<double> {
   AVM_FN static double uni(uint32_t hi, uint32_t lo) { return u53(hi, lo); }
   AVM_FN static double fma(double a, double b, double c) { return __builtin_fma(a, b, c); }
-  AVM_FN static double sqrt_(double x) { return sqrt(x); }
+  AVM_FN static double sqrt_(double x) { return sqrt_nn(x); }
   AVM_FN static double rsqrt_(double x) { return rsqrt(x); }
   AVM_FN static double log_(double x) { return log_pos(x); }
   AVM_FN static double floor_(double x) { return floor(x); }
@@ -485,7 +509,7 @@ AVM_FN uint32_t slab_exit(double z0, double vz, double az, double zlo, double zh
 // rotated to Cartesian.
 template <class R>
 AVM_FN void polar_field(const FieldDev& F, double x, double y, R& Ex, R& Ey) {
-  const double rho = sqrt(x * x + y * y);
+  const double rho = sqrt_nn(x * x + y * y);
   if (!(rho > 0.0)) {
     Ex = R(0);
     Ey = R(0);
@@ -752,9 +776,9 @@ AVM_FN HelixBound helix_bound(const FieldDev& F, const RunParams& P, double vx, 
   const double wz = F.wd_scale * (Ex * F.Bv[1] - Ey * F.Bv[0]);
   const double px = vx - vpar * bx, py = vy - vpar * by, pz = vz - vpar * bz;
   const double ux = px - wx, uy = py - wy, uz = pz - wz;
-  const double un = sqrt(ux * ux + uy * uy + uz * uz);
-  return HelixBound{fabs(vpar), fabs(apar), sqrt(px * px + py * py + pz * pz), un * F.omega,
-                    sqrt(wx * wx + wy * wy + wz * wz) + un};
+  const double un = sqrt_nn(ux * ux + uy * uy + uz * uz);
+  return HelixBound{fabs(vpar), fabs(apar), sqrt_nn(px * px + py * py + pz * pz), un * F.omega,
+                    sqrt_nn(wx * wx + wy * wy + wz * wz) + un};
 }
 
 // Smallest s >= 0 at which the bound reaches energy e_edge (0 if it is
@@ -1087,54 +1111,56 @@ AVM_FN int32_t flight_step(Elec<R>& e, const GasDev& G, const TabView<R>& T, con
     c = decide<double>(G, global_view<double>(G), en64, u53(w.w2, w.w3) * (double)gam, m64, over);
   }
   if (over) e.n_over += 1;
+  R e_band = en;  // energy whose band the next flight starts in
   if (c < 0) {
     if (c == -1)
       e.n_null += 1;
     else
       e.n_masked += 1;
     e.k += 1;
-    if (kBanded) e.band = band_of<R>(G, T, en);
-    return STEP_CONTINUE;
-  }
-  e.n_real += 1;
-  const int32_t kind = T.ch[c].kind;
-  if (kind == CH_ATTACHMENT) {
-    status = ST_ATTACHED;
-    return STEP_DONE;
-  }
-  if (kind == CH_IONISATION) {
-    // finished by complete_ionisation() (the caller batches it)
-    child.pen = en;
-    child.pc = c;
-    return STEP_IONISED;
-  }
-  const Block w1 = draw(P, e.aval, e.eid, e.k, 1);
-  const R uA = Mr::uni(w1.w0, w1.w1);
-  const R uB = Mr::uni(w1.w2, w1.w3);
-  const ChanP<R>& ch = T.ch[c];
-  R e_new, cos_t;
-  if (kind == CH_ELASTIC) {
-    const R cchi = ch.angular ? R(1) - R(2) * uA / Mr::fma(R(1) - uA, en * ch.inv_screen8, R(1))
-                              : R(1) - R(2) * uA;
-    e_new = en * (R(1) - ch.el_loss * (R(1) - cchi));
-    cos_t = (ch.mu + cchi) * Mr::rsqrt_(Mr::fma(ch.two_mu, cchi, ch.mu2p1));
-  } else {  // excitation
-    if (ch.pen_prob > R(0)) {
-      // Penning transfer, decided by the first uniform of block 2: the
-      // excitation and its transfer electron are finished with the
-      // ionisations after the pass
-      const Block w2 = draw(P, e.aval, e.eid, e.k, 2);
-      if (Mr::uni(w2.w0, w2.w1) < ch.pen_prob) {
-        child.pen = en;
-        child.pc = c;
-        return STEP_IONISED;
-      }
+  } else {
+    e.n_real += 1;
+    const int32_t kind = T.ch[c].kind;
+    if (kind == CH_ATTACHMENT) {
+      status = ST_ATTACHED;
+      return STEP_DONE;
     }
-    e_new = en - ch.loss;
-    cos_t = R(1) - R(2) * uA;
+    if (kind == CH_IONISATION) {
+      // finished by complete_ionisation() (the caller batches it)
+      child.pen = en;
+      child.pc = c;
+      return STEP_IONISED;
+    }
+    const Block w1 = draw(P, e.aval, e.eid, e.k, 1);
+    const R uA = Mr::uni(w1.w0, w1.w1);
+    const R uB = Mr::uni(w1.w2, w1.w3);
+    const ChanP<R>& ch = T.ch[c];
+    R e_new, cos_t;
+    if (kind == CH_ELASTIC) {
+      const R cchi = ch.angular ? R(1) - R(2) * uA / Mr::fma(R(1) - uA, en * ch.inv_screen8, R(1))
+                                : R(1) - R(2) * uA;
+      e_new = en * (R(1) - ch.el_loss * (R(1) - cchi));
+      cos_t = (ch.mu + cchi) * Mr::rsqrt_(Mr::fma(ch.two_mu, cchi, ch.mu2p1));
+    } else {  // excitation
+      if (ch.pen_prob > R(0)) {
+        // Penning transfer, decided by the first uniform of block 2: the
+        // excitation and its transfer electron are finished with the
+        // ionisations after the pass
+        const Block w2 = draw(P, e.aval, e.eid, e.k, 2);
+        if (Mr::uni(w2.w0, w2.w1) < ch.pen_prob) {
+          child.pen = en;
+          child.pc = c;
+          return STEP_IONISED;
+        }
+      }
+      e_new = en - ch.loss;
+      cos_t = R(1) - R(2) * uA;
+    }
+    scatter_to<R>(e, P, cos_t, uB, e_new);
+    e_band = e_new;
   }
-  scatter_to<R>(e, P, cos_t, uB, e_new);
-  if (kBanded) e.band = band_of<R>(G, T, e_new);
+  // one band search for the null and the real-collision paths
+  if (kBanded) e.band = band_of<R>(G, T, e_band);
   return STEP_CONTINUE;
 }
 
