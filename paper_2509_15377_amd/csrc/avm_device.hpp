@@ -183,6 +183,16 @@ AVM_FN const T& pinned(const T* p) {
   return *(p + pin_uniform(0u));
 }
 
+// a ^ b ^ c in one instruction (gfx950's three-input bitwise operation,
+// truth table 0x96)
+AVM_FN uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+#else
+  return a ^ b ^ c;
+#endif
+}
+
 AVM_FN Block philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1) {
   k0 = pin_uniform(k0);  // the round keys are formed here, not kept live
   k1 = pin_uniform(k1);
@@ -192,8 +202,8 @@ AVM_FN Block philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t
     const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
     const uint32_t lo0 = (uint32_t)p0, hi0 = (uint32_t)(p0 >> 32);
     const uint32_t lo1 = (uint32_t)p1, hi1 = (uint32_t)(p1 >> 32);
-    const uint32_t n0 = hi1 ^ c1 ^ k0;
-    const uint32_t n2 = hi0 ^ c3 ^ k1;
+    const uint32_t n0 = xor3(hi1, c1, k0);
+    const uint32_t n2 = xor3(hi0, c3, k1);
     c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
     k0 += 0x9E3779B9u;
     k1 += 0xBB67AE85u;
@@ -272,6 +282,19 @@ AVM_FN double sqrt_nn(double x) {
   return x > 0.0 ? g : 0.0;
 #else
   return x > 0.0 ? sqrt(x) : 0.0;
+#endif
+}
+
+// 1 / sqrt(x) for a positive normal x: the hardware estimate y0 refined by
+// the binomial series of (1 - e)^(-1/2) = 1 + e/2 + 3e^2/8 + ... with
+// e = 1 - x y0^2 (no handling of zero, infinite or negative arguments).
+AVM_FN double rsqrt_pos(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  const double y = __builtin_amdgcn_rsq(x);
+  const double e = __builtin_fma(y * -x, y, 1.0);
+  return __builtin_fma(y * e, __builtin_fma(e, 0.375, 0.5), y);
+#else
+  return 1.0 / sqrt(x);
 #endif
 }
 
@@ -362,7 +385,7 @@ template <> struct M<double> {
   AVM_FN static double uni(uint32_t hi, uint32_t lo) { return u53(hi, lo); }
   AVM_FN static double fma(double a, double b, double c) { return __builtin_fma(a, b, c); }
   AVM_FN static double sqrt_(double x) { return sqrt_nn(x); }
-  AVM_FN static double rsqrt_(double x) { return rsqrt(x); }
+  AVM_FN static double rsqrt_(double x) { return rsqrt_pos(x); }
   AVM_FN static double log_(double x) { return log_pos(x); }
   AVM_FN static double floor_(double x) { return floor(x); }
   AVM_FN static double tan_(double x) { return tan(x); }
