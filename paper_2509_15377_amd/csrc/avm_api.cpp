@@ -328,6 +328,8 @@ avm_status avm_gas_create(int32_t device, double e_max_eV, int32_t n_bins, doubl
   D.gamma_f = gf;
   D.inv_gamma_f = 1.0f / gf;
   D.scale_f = (float)D.scale;
+  D.x_top = (double)n_bins;
+  D.x_top_f = (float)n_bins;
   D.band_scale_f = (float)D.band_scale;
   *out = g;
   return AVM_OK;

@@ -95,12 +95,17 @@ struct GasDev {
   double band_scale;        // n_bins / (E_max * band_bins): first guess of the band
   float gamma_f, inv_gamma_f, scale_f, band_scale_f;
   int32_t n_bins, n_ch, n_bands, band_bins;
+  double x_top;             // n_bins as a double (the table's end in bin units)
+  float x_top_f;            // n_bins as a float
 };
 
-// Where the hot tables are read from: `tot` and `cum0` hold nodes
-// [0, n_lo) of the total rate and of cumulative column 0 (LDS copies in the
-// persistent kernel, the global arrays elsewhere); band tables likewise.
-// Both sources hold the same values, so results do not depend on the view.
+// Where the hot tables are read from.  TabView: the global arrays (`tot`
+// and `cum0` hold nodes [0, n_lo) of the total rate and of cumulative
+// column 0).  TabLds: the persistent kernel's LDS copies -- the first n_lo
+// nodes of those two, the first kLdsBands bands and the first kLdsChannels
+// channels -- with reads of higher band or channel indices going to the
+// global arrays.  Both sources hold the same values, so results do not
+// depend on the view.
 template <class R>
 struct TabView {
   const R* tot;
@@ -110,6 +115,29 @@ struct TabView {
   const R* binv;
   const R* bedge;
   const ChanP<R>* ch;  // channel parameters
+};
+
+constexpr int kLdsBands = 512;    // band tables staged in LDS (the first this many)
+constexpr int kLdsChannels = 64;  // channel parameters staged in LDS (the first this many)
+
+// Pointers into LDS, typed as such in device code: loads through them are
+// DS instructions (a pointer that may hold either an LDS or a global address
+// is read with the slower FLAT instructions).
+#if defined(__HIP_DEVICE_COMPILE__)
+#define AVM_LDS __attribute__((address_space(3)))
+#else
+#define AVM_LDS
+#endif
+
+template <class R>
+struct TabLds {
+  const AVM_LDS R* tot;
+  const AVM_LDS R* cum0;
+  int32_t n_lo;
+  const AVM_LDS R* bgam;
+  const AVM_LDS R* binv;
+  const AVM_LDS R* bedge;
+  const AVM_LDS ChanP<R>* ch;
 };
 
 enum FieldKind : int32_t { FIELD_SLAB = 0, FIELD_POLAR = 1 };
@@ -599,6 +627,7 @@ enum : int32_t { STEP_CONTINUE = 0, STEP_IONISED = 1, STEP_DONE = 2 };
 template <class R> struct Sel;
 template <> struct Sel<double> {
   AVM_FN static double scale(const GasDev& G) { return G.scale; }
+  AVM_FN static double x_top(const GasDev& G) { return G.x_top; }
   AVM_FN static double band_scale(const GasDev& G) { return G.band_scale; }
   AVM_FN static double gamma(const GasDev& G) { return G.gamma; }
   AVM_FN static double inv_gamma(const GasDev& G) { return G.inv_gamma; }
@@ -606,12 +635,16 @@ template <> struct Sel<double> {
   AVM_FN static const double* total(const GasDev& G) { return G.total; }
   AVM_FN static const double* cum0(const GasDev& G) { return G.cum0; }
   AVM_FN static const double* cum(const GasDev& G) { return G.cum; }
+  AVM_FN static const double* bgam(const GasDev& G) { return G.band_gamma; }
+  AVM_FN static const double* binv(const GasDev& G) { return G.band_inv; }
+  AVM_FN static const double* bedge(const GasDev& G) { return G.band_edge; }
   AVM_FN static double k_a(const RunParams& P) { return P.k_a; }
   AVM_FN static double two_ka(const RunParams& P) { return P.two_ka; }
   AVM_FN static double inv_2ka(const RunParams& P) { return P.inv_2ka; }
 };
 template <> struct Sel<float> {
   AVM_FN static float scale(const GasDev& G) { return G.scale_f; }
+  AVM_FN static float x_top(const GasDev& G) { return G.x_top_f; }
   AVM_FN static float band_scale(const GasDev& G) { return G.band_scale_f; }
   AVM_FN static float gamma(const GasDev& G) { return G.gamma_f; }
   AVM_FN static float inv_gamma(const GasDev& G) { return G.inv_gamma_f; }
@@ -619,6 +652,9 @@ template <> struct Sel<float> {
   AVM_FN static const float* total(const GasDev& G) { return G.total_f; }
   AVM_FN static const float* cum0(const GasDev& G) { return G.cum0_f; }
   AVM_FN static const float* cum(const GasDev& G) { return G.cum_f; }
+  AVM_FN static const float* bgam(const GasDev& G) { return G.band_gamma_f; }
+  AVM_FN static const float* binv(const GasDev& G) { return G.band_inv_f; }
+  AVM_FN static const float* bedge(const GasDev& G) { return G.band_edge_f; }
   AVM_FN static float k_a(const RunParams& P) { return P.k_a_f; }
   AVM_FN static float two_ka(const RunParams& P) { return P.two_ka_f; }
   AVM_FN static float inv_2ka(const RunParams& P) { return P.inv_2ka_f; }
@@ -634,12 +670,41 @@ template <> AVM_FN TabView<float> global_view<float>(const GasDev& G) {
                         G.band_edge_f, G.ch_f};
 }
 
+// Band tables and channel parameters through either view.  Beyond the LDS
+// copies the global pointer is read from the kernel argument where it is
+// used (pinned), so it does not occupy registers across the loop.
 template <class R>
-AVM_FN int32_t band_of(const GasDev& G, const TabView<R>& T, R e) {
+AVM_FN R band_gamma(const GasDev&, const TabView<R>& T, int32_t b) { return T.bgam[b]; }
+template <class R>
+AVM_FN R band_inv(const GasDev&, const TabView<R>& T, int32_t b) { return T.binv[b]; }
+template <class R>
+AVM_FN R band_edge(const GasDev&, const TabView<R>& T, int32_t b) { return T.bedge[b]; }
+template <class R>
+AVM_FN ChanP<R> chan(const GasDev&, const TabView<R>& T, int32_t c) { return T.ch[c]; }
+template <class R>
+AVM_FN R band_gamma(const GasDev& G, const TabLds<R>& T, int32_t b) {
+  return b < kLdsBands ? T.bgam[b] : Sel<R>::bgam(pinned(&G))[b];
+}
+template <class R>
+AVM_FN R band_inv(const GasDev& G, const TabLds<R>& T, int32_t b) {
+  return b < kLdsBands ? T.binv[b] : Sel<R>::binv(pinned(&G))[b];
+}
+template <class R>
+AVM_FN R band_edge(const GasDev& G, const TabLds<R>& T, int32_t b) {
+  return b < kLdsBands ? T.bedge[b] : Sel<R>::bedge(pinned(&G))[b];
+}
+template <class R>
+AVM_FN ChanP<R> chan(const GasDev& G, const TabLds<R>& T, int32_t c) {
+  if (c < kLdsChannels) return T.ch[c];
+  return Sel<R>::ch(pinned(&G))[c];
+}
+
+template <class R, class TV>
+AVM_FN int32_t band_of(const GasDev& G, const TV& T, R e) {
   int32_t b = (int32_t)(e * Sel<R>::band_scale(G));
   b = b < 0 ? 0 : (b > G.n_bands - 1 ? G.n_bands - 1 : b);
-  while (b < G.n_bands - 1 && !(e < T.bedge[b])) ++b;
-  while (b > 0 && e < T.bedge[b - 1]) --b;
+  while (b < G.n_bands - 1 && !(e < band_edge(G, T, b))) ++b;
+  while (b > 0 && e < band_edge(G, T, b - 1)) --b;
   return b;
 }
 
@@ -876,13 +941,13 @@ AVM_FN void scatter_to(Elec<R>& e, const RunParams& P, R cos_t, R uB, R e_new) {
 // `margin` returns the smallest relative distance of r_sel to a rate it was
 // compared with, or of en to the window edge it was compared with; `over`
 // tells whether en lies above the table.
-template <class R>
-AVM_FN int decide(const GasDev& G, const TabView<R>& T, R en, R r_sel, R& margin, bool& over) {
+template <class R, class TV>
+AVM_FN int decide(const GasDev& G, const TV& T, R en, R r_sel, R& margin, bool& over) {
   using Mr = M<R>;
   const R x = en * Sel<R>::scale(G);
   int32_t kb;
   R f;
-  over = !(x < (R)G.n_bins);
+  over = !(x < Sel<R>::x_top(G));
   if (over) {
     kb = G.n_bins;
     f = R(0);
@@ -956,8 +1021,9 @@ AVM_FN int decide(const GasDev& G, const TabView<R>& T, R en, R r_sel, R& margin
     c = lo;
   }
   margin = mg / r_sel;
-  const double e_lo = T.ch[c].e_lo;
-  const double e_hi = T.ch[c].e_hi;
+  const ChanP<R> cw = chan(G, T, c);
+  const double e_lo = cw.e_lo;
+  const double e_hi = cw.e_hi;
   const double ed = (double)en;
   if (sizeof(R) == 4) {
     const double dl = fabs(ed - e_lo), dh = fabs(ed - e_hi);
@@ -973,8 +1039,8 @@ AVM_FN int decide(const GasDev& G, const TabView<R>& T, R en, R r_sel, R& margin
 // energy in `child`) when the collision is an ionisation -- the caller then
 // finishes it with complete_ionisation() before the next pass -- otherwise
 // STEP_CONTINUE.
-template <class R, bool kBanded, int kField, bool kSignal = false>
-AVM_FN int32_t flight_step(Elec<R>& e, const GasDev& G, const TabView<R>& T, const FieldDev& F,
+template <class R, bool kBanded, int kField, bool kSignal = false, class TV>
+AVM_FN int32_t flight_step(Elec<R>& e, const GasDev& G, const TV& T, const FieldDev& F,
                            const RunParams& P, Child<R>& child, uint32_t& status,
                            const SignalDev* Q = nullptr) {
   using Mr = M<R>;
@@ -1011,7 +1077,7 @@ AVM_FN int32_t flight_step(Elec<R>& e, const GasDev& G, const TabView<R>& T, con
     // lookahead: raise the band to the band of the energy after `look` mean
     // free times of the current band (the flight energy, or its helical
     // bound); the choice uses only the state at the flight start
-    const double s_look = P.look * (double)T.binv[e.band];
+    const double s_look = P.look * (double)band_inv(G, T, e.band);
     R e_look;
     if (helical) {
       const double vpar = hb.vp + hb.ap * s_look;
@@ -1027,17 +1093,17 @@ AVM_FN int32_t flight_step(Elec<R>& e, const GasDev& G, const TabView<R>& T, con
     if (bl > e.band) e.band = bl;
   }
   if (helical)
-    while (e.band < G.n_bands - 1 && (hb.vp * hb.vp + hb.p * hb.p) * P.inv_2ka >= (double)T.bedge[e.band])
+    while (e.band < G.n_bands - 1 && (hb.vp * hb.vp + hb.p * hb.p) * P.inv_2ka >= (double)band_edge(G, T, e.band))
       e.band += 1;
-  const R gam = kBanded ? T.bgam[e.band] : Sel<R>::gamma(G);
-  const R inv_gam = kBanded ? T.binv[e.band] : Sel<R>::inv_gamma(G);
+  const R gam = kBanded ? band_gamma(G, T, e.band) : Sel<R>::gamma(G);
+  const R inv_gam = kBanded ? band_inv(G, T, e.band) : Sel<R>::inv_gamma(G);
   const R tau = -Mr::log_(u1) * inv_gam;
   R tau_end = tau;
   int cut = 0;  // 1: band edge, 2: time limit
   if (helical) {
     if (e.band < G.n_bands - 1) {
       // cut where the energy bound reaches the edge: Gamma_b holds before
-      const double tc = helix_root(hb, P, (double)T.bedge[e.band]);
+      const double tc = helix_root(hb, P, (double)band_edge(G, T, e.band));
       if (tc < (double)tau_end) {
         tau_end = down_to<R>(tc);
         cut = 1;
@@ -1045,7 +1111,7 @@ AVM_FN int32_t flight_step(Elec<R>& e, const GasDev& G, const TabView<R>& T, con
     }
   } else if (kBanded && e.band < G.n_bands - 1) {
     const R fx = Mr::fma(ax, tau, e.vx), fy = Mr::fma(ay, tau, e.vy), fz = Mr::fma(az, tau, e.vz);
-    const R edge = T.bedge[e.band];
+    const R edge = band_edge(G, T, e.band);
     if (dot3<R>(fx, fy, fz, fx, fy, fz) * Sel<R>::inv_2ka(P) >= edge) {
       const R tc = band_crossing<R>(P, e, ax, ay, az, edge);
       if (tc < tau_end) {
@@ -1143,7 +1209,8 @@ AVM_FN int32_t flight_step(Elec<R>& e, const GasDev& G, const TabView<R>& T, con
     e.k += 1;
   } else {
     e.n_real += 1;
-    const int32_t kind = T.ch[c].kind;
+    const ChanP<R> ch = chan(G, T, c);
+    const int32_t kind = ch.kind;
     if (kind == CH_ATTACHMENT) {
       status = ST_ATTACHED;
       return STEP_DONE;
@@ -1157,7 +1224,6 @@ AVM_FN int32_t flight_step(Elec<R>& e, const GasDev& G, const TabView<R>& T, con
     const Block w1 = draw(P, e.aval, e.eid, e.k, 1);
     const R uA = Mr::uni(w1.w0, w1.w1);
     const R uB = Mr::uni(w1.w2, w1.w3);
-    const ChanP<R>& ch = T.ch[c];
     R e_new, cos_t;
     if (kind == CH_ELASTIC) {
       const R cchi = ch.angular ? R(1) - R(2) * uA / Mr::fma(R(1) - uA, en * ch.inv_screen8, R(1))
@@ -1191,12 +1257,12 @@ AVM_FN int32_t flight_step(Elec<R>& e, const GasDev& G, const TabView<R>& T, con
 // (blocks j = 1..3 of the electron's flight k): energy split (transfer: the
 // channel's transfer energy, the electron keeps e - threshold), the
 // electron's new direction, the secondary's energy, direction and id.
-template <class R, bool kBanded>
-AVM_FN void complete_ionisation(Elec<R>& e, const GasDev& G, const TabView<R>& T,
+template <class R, bool kBanded, class TV>
+AVM_FN void complete_ionisation(Elec<R>& e, const GasDev& G, const TV& T,
                                 const RunParams& P, Child<R>& child) {
   using Mr = M<R>;
   const int c = child.pc;
-  const ChanP<R>& ch = T.ch[c];
+  const ChanP<R> ch = chan(G, T, c);
   const R avail = child.pen - ch.loss;
   const Block w1 = draw(P, e.aval, e.eid, e.k, 1);
   const Block w2 = draw(P, e.aval, e.eid, e.k, 2);

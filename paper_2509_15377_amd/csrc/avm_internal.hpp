@@ -13,16 +13,25 @@ namespace avm {
 // the s-th electron created: its start record (written when it is created)
 // and its end record (written when it terminates).  The plain mode also
 // keeps the state of live electrons between transport iterations in the end
-// record (x1..t1 = current position, v1 = current velocity).
+// record (x1..t1 = current position, v1 = current velocity).  In device code
+// the pointers are typed as global memory (same 64-bit layout), so accesses
+// are global instructions with a scalar base rather than FLAT ones (only in
+// the translation unit of the kernels, which defines AVM_KERNELS_TU; host
+// code elsewhere sees plain pointers).
+#if defined(__HIP_DEVICE_COMPILE__) && defined(AVM_KERNELS_TU)
+#define AVM_GLB __attribute__((address_space(1)))
+#else
+#define AVM_GLB
+#endif
 struct Store {
-  double *x0, *y0, *z0, *t0, *vx0, *vy0, *vz0, *e0;
-  uint64_t *eid, *parent;
-  uint32_t* aval;
-  uint32_t* qready;  // batched: queue entry q published when qready[q] == epoch
-  uint32_t* qslot;   // batched: slot of queue entry q
-  double *x1, *y1, *z1, *t1, *e1, *vx1, *vy1, *vz1;
-  uint32_t *k1, *band1;
-  uint32_t *status, *n_real, *n_ion, *n_null, *n_masked, *n_band, *n_over;
+  AVM_GLB double *x0, *y0, *z0, *t0, *vx0, *vy0, *vz0, *e0;
+  AVM_GLB uint64_t *eid, *parent;
+  AVM_GLB uint32_t* aval;
+  AVM_GLB uint32_t* qready;  // batched: queue entry q published when qready[q] == epoch
+  AVM_GLB uint32_t* qslot;   // batched: slot of queue entry q
+  AVM_GLB double *x1, *y1, *z1, *t1, *e1, *vx1, *vy1, *vz1;
+  AVM_GLB uint32_t *k1, *band1;
+  AVM_GLB uint32_t *status, *n_real, *n_ion, *n_null, *n_masked, *n_band, *n_over;
   uint64_t capacity;
 };
 

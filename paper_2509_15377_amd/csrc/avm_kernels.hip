@@ -2,6 +2,7 @@
 // load, the plain generation-synchronous transport iteration, the batched
 // persistent transport kernel with its device work queue, and the
 // statistics reduction.
+#define AVM_KERNELS_TU 1  // device pointers of the run store typed as global memory
 #include "avm_internal.hpp"
 
 namespace avm {
@@ -17,8 +18,6 @@ constexpr int kBlock = 256;        // set-up, plain and statistics kernels
 #endif
 constexpr int kPBlock = AVM_PBLOCK;
 constexpr int kLdsBytes = 24576;   // bytes of each table slice staged in LDS
-constexpr int kLdsBands = 512;     // band tables staged in LDS up to this size
-constexpr int kLdsChannels = 64;   // channel parameters staged in LDS up to this many
 
 // ---------------------------------------------------------------------------
 // wave-level helpers (wave64)
@@ -218,8 +217,8 @@ AVM_FN void write_start(const Store& S, uint64_t s, const Elec<R>& parent, const
 
 // Counters, band and (slab) field of an electron whose position, velocity,
 // id and avalanche are set.
-template <class R, bool kBanded, int kField>
-AVM_FN void load_elec_tail(const GasDev& G, const TabView<R>& T, const FieldDev& F,
+template <class R, bool kBanded, int kField, class TV>
+AVM_FN void load_elec_tail(const GasDev& G, const TV& T, const FieldDev& F,
                            const RunParams& P, Elec<R>& e) {
   e.k = 0;
   e.n_real = 0; e.n_ion = 0; e.n_null = 0; e.n_masked = 0; e.n_band = 0; e.n_over = 0;
@@ -312,18 +311,18 @@ __global__ void __launch_bounds__(kBlock) k_generation(GasDev G, FieldDev F, Run
 // one wave to another: they are performed at the device's point of
 // coherence, so they need no L2 write-back or invalidation (which the
 // release/acquire forms would issue on every XCD-local L2).
-AVM_FN void st_coh(double* p, double v) {
-  __hip_atomic_store(reinterpret_cast<unsigned long long*>(p), __builtin_bit_cast(unsigned long long, v),
+AVM_FN void st_coh(AVM_GLB double* p, double v) {
+  __hip_atomic_store(reinterpret_cast<AVM_GLB unsigned long long*>(p), __builtin_bit_cast(unsigned long long, v),
                      __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-AVM_FN void st_coh(uint64_t* p, uint64_t v) {
+AVM_FN void st_coh(AVM_GLB uint64_t* p, uint64_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-AVM_FN void st_coh(uint32_t* p, uint32_t v) {
+AVM_FN void st_coh(AVM_GLB uint32_t* p, uint32_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-AVM_FN double ld_coh(const double* p) {
-  return __builtin_bit_cast(double, __hip_atomic_load(reinterpret_cast<const unsigned long long*>(p),
+AVM_FN double ld_coh(const AVM_GLB double* p) {
+  return __builtin_bit_cast(double, __hip_atomic_load(reinterpret_cast<const AVM_GLB unsigned long long*>(p),
                                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
 }
 template <class T>
@@ -402,22 +401,19 @@ __global__ void __launch_bounds__(kPBlock)
     s_tot[k] = Tg.tot[k];
     s_cum0[k] = Tg.cum0[k];
   }
-  const bool bands_lds = G.n_bands <= kLdsBands;
-  if (bands_lds)
-    for (int b = threadIdx.x; b < G.n_bands; b += kPBlock) {
-      s_bg[b] = Tg.bgam[b];
-      s_bi[b] = Tg.binv[b];
-      s_be[b] = Tg.bedge[b];
-    }
-  const bool ch_lds = G.n_ch <= kLdsChannels;
-  if (ch_lds && (int)threadIdx.x < G.n_ch) s_ch[threadIdx.x] = Tg.ch[threadIdx.x];
-  __syncthreads();
-  TabView<R> T{s_tot, s_cum0, n_lo, Tg.bgam, Tg.binv, Tg.bedge, ch_lds ? s_ch : Tg.ch};
-  if (bands_lds) {
-    T.bgam = s_bg;
-    T.binv = s_bi;
-    T.bedge = s_be;
+  // the first kLdsBands bands and kLdsChannels channels (the accessors read
+  // higher indices from the global arrays)
+  const int n_lb = G.n_bands < kLdsBands ? G.n_bands : kLdsBands;
+  for (int b = threadIdx.x; b < n_lb; b += kPBlock) {
+    s_bg[b] = Tg.bgam[b];
+    s_bi[b] = Tg.binv[b];
+    s_be[b] = Tg.bedge[b];
   }
+  const int n_lc = G.n_ch < kLdsChannels ? G.n_ch : kLdsChannels;
+  if ((int)threadIdx.x < n_lc) s_ch[threadIdx.x] = Tg.ch[threadIdx.x];
+  __syncthreads();
+  const TabLds<R> T{(const AVM_LDS R*)s_tot, (const AVM_LDS R*)s_cum0, n_lo, (const AVM_LDS R*)s_bg,
+                    (const AVM_LDS R*)s_bi, (const AVM_LDS R*)s_be, (const AVM_LDS ChanP<R>*)s_ch};
   Xfer& X = xfer_all[threadIdx.x >> 6];
   const uint32_t lane = __lane_id();
   bool has = false, cp = false;
