@@ -1045,15 +1045,11 @@ AVM_FN int32_t flight_step(Elec<R>& e, const GasDev& G, const TV& T, const Field
                            const SignalDev* Q = nullptr) {
   using Mr = M<R>;
   constexpr bool kMixed = sizeof(R) == 4;
-  // position valid?
-  status = region_status<R>(F, e);
-  if (status) return STEP_DONE;
-  if (e.k >= P.k_max) {
-    status = ST_ABANDONED;
-    return STEP_DONE;
-  }
-  if (e.t >= P.t_max) {
-    status = ST_TIME;
+  // position valid, flights and time left?
+  uint32_t st0 = region_status<R>(F, e);
+  st0 = st0 ? st0 : (e.k >= P.k_max ? (uint32_t)ST_ABANDONED : (e.t >= P.t_max ? (uint32_t)ST_TIME : 0u));
+  if (st0) {
+    status = st0;
     return STEP_DONE;
   }
   const Block w = draw(P, e.aval, e.eid, e.k, 0);
@@ -1165,92 +1161,91 @@ AVM_FN int32_t flight_step(Elec<R>& e, const GasDev& G, const TV& T, const Field
                                                    e.t + (side ? s_exit : (double)tau_end));
   e.x = rx; e.y = ry; e.z = rz;
   e.vx = ux; e.vy = uy; e.vz = uz;
-  if (side) {
-    e.t = e.t + s_exit;
-    status = side;
-    return STEP_DONE;
-  }
-  e.t = e.t + (double)tau_end;
-  if (cut == 2) {
-    status = ST_TIME;
-    return STEP_DONE;
-  }
-  if (kBanded && cut == 1) {
-    // restart at the band edge with the next majorant; the band index is
-    // advanced explicitly, never re-derived from the rounded energy
-    e.band += 1;
-    e.n_band += 1;
-    e.k += 1;
-    return STEP_CONTINUE;
-  }
-  // collision?
-  const R en = dot3<R>(e.vx, e.vy, e.vz, e.vx, e.vy, e.vz) * Sel<R>::inv_2ka(P);
-  if (!(en < Mr::inf())) {
-    status = ST_ERROR;
-    return STEP_DONE;
-  }
-  R margin;
-  bool over;
-  int c = decide<R>(G, T, en, u2 * gam, margin, over);
-  if (kMixed && margin <= R(3.814697265625e-6)) {
-    // too close to call in FP32: decide again in FP64 for this state
-    const double vx = (double)e.vx, vy = (double)e.vy, vz = (double)e.vz;
-    const double en64 = dot3<double>(vx, vy, vz, vx, vy, vz) * P.inv_2ka;
-    double m64;
-    c = decide<double>(G, global_view<double>(G), en64, u53(w.w2, w.w3) * (double)gam, m64, over);
-  }
-  if (over) e.n_over += 1;
-  R e_band = en;  // energy whose band the next flight starts in
-  if (c < 0) {
-    if (c == -1)
-      e.n_null += 1;
-    else
-      e.n_masked += 1;
-    e.k += 1;
-  } else {
-    e.n_real += 1;
-    const ChanP<R> ch = chan(G, T, c);
-    const int32_t kind = ch.kind;
-    if (kind == CH_ATTACHMENT) {
-      status = ST_ATTACHED;
-      return STEP_DONE;
-    }
-    if (kind == CH_IONISATION) {
-      // finished by complete_ionisation() (the caller batches it)
-      child.pen = en;
-      child.pc = c;
-      return STEP_IONISED;
-    }
-    const Block w1 = draw(P, e.aval, e.eid, e.k, 1);
-    const R uA = Mr::uni(w1.w0, w1.w1);
-    const R uB = Mr::uni(w1.w2, w1.w3);
-    R e_new, cos_t;
-    if (kind == CH_ELASTIC) {
-      const R cchi = ch.angular ? R(1) - R(2) * uA / Mr::fma(R(1) - uA, en * ch.inv_screen8, R(1))
-                                : R(1) - R(2) * uA;
-      e_new = en * (R(1) - ch.el_loss * (R(1) - cchi));
-      cos_t = (ch.mu + cchi) * Mr::rsqrt_(Mr::fma(ch.two_mu, cchi, ch.mu2p1));
-    } else {  // excitation
-      if (ch.pen_prob > R(0)) {
-        // Penning transfer, decided by the first uniform of block 2: the
-        // excitation and its transfer electron are finished with the
-        // ionisations after the pass
-        const Block w2 = draw(P, e.aval, e.eid, e.k, 2);
-        if (Mr::uni(w2.w0, w2.w1) < ch.pen_prob) {
-          child.pen = en;
-          child.pc = c;
-          return STEP_IONISED;
+  e.t = e.t + (side ? s_exit : (double)tau_end);
+  // the rest runs to a single exit: the outcome is kept in `st` (a
+  // termination status) and `ret`, so the paths share one join
+  uint32_t st = side ? side : (cut == 2 ? (uint32_t)ST_TIME : 0u);
+  int32_t ret = STEP_CONTINUE;
+  if (st == 0) {
+    if (kBanded && cut == 1) {
+      // restart at the band edge with the next majorant; the band index is
+      // advanced explicitly, never re-derived from the rounded energy
+      e.band += 1;
+      e.n_band += 1;
+      e.k += 1;
+    } else {
+      // collision?
+      const R en = dot3<R>(e.vx, e.vy, e.vz, e.vx, e.vy, e.vz) * Sel<R>::inv_2ka(P);
+      if (!(en < Mr::inf())) {
+        st = ST_ERROR;
+      } else {
+        R margin;
+        bool over;
+        int c = decide<R>(G, T, en, u2 * gam, margin, over);
+        if (kMixed && margin <= R(3.814697265625e-6)) {
+          // too close to call in FP32: decide again in FP64 for this state
+          const double vx = (double)e.vx, vy = (double)e.vy, vz = (double)e.vz;
+          const double en64 = dot3<double>(vx, vy, vz, vx, vy, vz) * P.inv_2ka;
+          double m64;
+          c = decide<double>(G, global_view<double>(G), en64, u53(w.w2, w.w3) * (double)gam, m64, over);
         }
+        if (over) e.n_over += 1;
+        R e_band = en;  // energy whose band the next flight starts in
+        if (c < 0) {
+          if (c == -1)
+            e.n_null += 1;
+          else
+            e.n_masked += 1;
+          e.k += 1;
+        } else {
+          e.n_real += 1;
+          const ChanP<R> ch = chan(G, T, c);
+          const int32_t kind = ch.kind;
+          if (kind == CH_ATTACHMENT) {
+            st = ST_ATTACHED;
+          } else if (kind == CH_IONISATION) {
+            // finished by complete_ionisation() (the caller batches it)
+            child.pen = en;
+            child.pc = c;
+            ret = STEP_IONISED;
+          } else {
+            const Block w1 = draw(P, e.aval, e.eid, e.k, 1);
+            const R uA = Mr::uni(w1.w0, w1.w1);
+            const R uB = Mr::uni(w1.w2, w1.w3);
+            R e_new = en, cos_t = R(1);
+            if (kind == CH_ELASTIC) {
+              const R cchi = ch.angular ? R(1) - R(2) * uA / Mr::fma(R(1) - uA, en * ch.inv_screen8, R(1))
+                                        : R(1) - R(2) * uA;
+              e_new = en * (R(1) - ch.el_loss * (R(1) - cchi));
+              cos_t = (ch.mu + cchi) * Mr::rsqrt_(Mr::fma(ch.two_mu, cchi, ch.mu2p1));
+            } else {  // excitation
+              if (ch.pen_prob > R(0)) {
+                // Penning transfer, decided by the first uniform of block 2:
+                // the excitation and its transfer electron are finished with
+                // the ionisations after the pass
+                const Block w2 = draw(P, e.aval, e.eid, e.k, 2);
+                if (Mr::uni(w2.w0, w2.w1) < ch.pen_prob) {
+                  child.pen = en;
+                  child.pc = c;
+                  ret = STEP_IONISED;
+                }
+              }
+              e_new = en - ch.loss;
+              cos_t = R(1) - R(2) * uA;
+            }
+            if (ret == STEP_CONTINUE) {
+              scatter_to<R>(e, P, cos_t, uB, e_new);
+              e_band = e_new;
+            }
+          }
+        }
+        // one band search for the null and the real-collision paths
+        if (kBanded && st == 0 && ret == STEP_CONTINUE) e.band = band_of<R>(G, T, e_band);
       }
-      e_new = en - ch.loss;
-      cos_t = R(1) - R(2) * uA;
     }
-    scatter_to<R>(e, P, cos_t, uB, e_new);
-    e_band = e_new;
   }
-  // one band search for the null and the real-collision paths
-  if (kBanded) e.band = band_of<R>(G, T, e_band);
-  return STEP_CONTINUE;
+  status = st;
+  return st ? STEP_DONE : ret;
 }
 
 // Finishes an ionisation (or a Penning transfer) decided by flight_step
