@@ -913,7 +913,8 @@ AVM_FN R band_crossing(const RunParams& P, const Elec<R>& e, R ax, R ay, R az, R
 }
 
 // New velocity after a real collision: the old direction turned by
-// (cos_t, phi = 2 pi uB), speed from the new energy; flight index advanced.
+// (cos_t, phi = 2 pi uB), speed from the new energy.  (The caller advances
+// the flight index.)
 template <class R>
 AVM_FN void scatter_to(Elec<R>& e, const RunParams& P, R cos_t, R uB, R e_new) {
   const R v2 = dot3<R>(e.vx, e.vy, e.vz, e.vx, e.vy, e.vz);
@@ -930,7 +931,6 @@ AVM_FN void scatter_to(Elec<R>& e, const RunParams& P, R cos_t, R uB, R e_new) {
   e.vx = sp1 * ox;
   e.vy = sp1 * oy;
   e.vz = sp1 * oz;
-  e.k += 1;
 }
 
 // Collision decision at energy en with selection value r_sel: -1 null,
@@ -1172,7 +1172,6 @@ AVM_FN int32_t flight_step(Elec<R>& e, const GasDev& G, const TV& T, const Field
       // advanced explicitly, never re-derived from the rounded energy
       e.band += 1;
       e.n_band += 1;
-      e.k += 1;
     } else {
       // collision?
       const R en = dot3<R>(e.vx, e.vy, e.vz, e.vx, e.vy, e.vz) * Sel<R>::inv_2ka(P);
@@ -1196,7 +1195,6 @@ AVM_FN int32_t flight_step(Elec<R>& e, const GasDev& G, const TV& T, const Field
             e.n_null += 1;
           else
             e.n_masked += 1;
-          e.k += 1;
         } else {
           e.n_real += 1;
           const ChanP<R> ch = chan(G, T, c);
@@ -1244,6 +1242,10 @@ AVM_FN int32_t flight_step(Elec<R>& e, const GasDev& G, const TV& T, const Field
       }
     }
   }
+  // every flight that goes on (null or masked collision, band cut, real
+  // collision) advances the flight index; an ionisation's is advanced when
+  // it is completed (its blocks j = 1..3 belong to this index)
+  if (st == 0 && ret == STEP_CONTINUE) e.k += 1;
   status = st;
   return st ? STEP_DONE : ret;
 }
@@ -1289,6 +1291,7 @@ AVM_FN void complete_ionisation(Elec<R>& e, const GasDev& G, const TV& T,
   child.eid = (((uint64_t)w3.w3 << 32) | (uint64_t)w3.w2) & 0x7FFFFFFFFFFFFFFFull;
   e.n_ion += 1;
   scatter_to<R>(e, P, R(1) - R(2) * uA, uB, e_new);
+  e.k += 1;
   if (kBanded) e.band = band_of<R>(G, T, e_new);
 }
 
