@@ -511,17 +511,17 @@ AVM_FN int roots2(R A, R B, R C, R& r1, R& r2) {
 AVM_FN uint32_t slab_exit(double z0, double vz, double az, double zlo, double zhi, double T,
                           double& s_exit) {
   const double zT = __builtin_fma(0.5 * az * T, T, __builtin_fma(vz, T, z0));
-  double zmin = z0 < zT ? z0 : zT;
-  double zmax = z0 > zT ? z0 : zT;
-  // the vertex s* = -vz/az lies in (0, T) iff vz az < 0 and |vz| < |az| T
-  if (vz * az < 0.0 && fabs(vz) < fabs(az) * T) {
-    const double zv = z0 - 0.5 * vz * vz / az;
-    zmin = zmin < zv ? zmin : zv;
-    zmax = zmax > zv ? zmax : zv;
-  }
   // margin: a relative 1e-12 of the coordinates keeps the filter conservative
   const double m = 1e-12 * (fabs(z0) + fabs(zhi) + fabs(zlo) + fabs(vz * T) + fabs(az * T * T));
-  if (zmax < zhi - m && zmin > zlo + m) return 0;
+  const double lo = zlo + m, hi = zhi - m;
+  bool inside = (z0 > zT ? z0 : zT) < hi && (z0 < zT ? z0 : zT) > lo;
+  // the vertex s* = -vz/az lies in (0, T) iff vz az < 0 and |vz| < |az| T;
+  // there z = z0 - vz^2 / (2 az), a minimum for az > 0 (to stay above lo)
+  // and a maximum for az < 0 (to stay below hi): compared after multiplying
+  // by 2 az, without a division
+  if (inside && vz * az < 0.0 && fabs(vz) < fabs(az) * T)
+    inside = 2.0 * az * (z0 - (az > 0.0 ? lo : hi)) > vz * vz;
+  if (inside) return 0;
   double best = __builtin_inf();
   uint32_t side = 0;
   double r1 = 0.0, r2 = 0.0;
@@ -909,7 +909,9 @@ AVM_FN R band_crossing(const RunParams& P, const Elec<R>& e, R ax, R ay, R az, R
   if (A == R(0)) return R(0);
   const R B = R(2) * dot3<R>(e.vx, e.vy, e.vz, ax, ay, az);
   const R sq = M<R>::sqrt_(B * B - R(4) * A * C);
-  return B > R(0) ? (R(-2) * C) / (B + sq) : (sq - B) / (R(2) * A);
+  // the stable form of the positive root, with one division
+  const bool pos = B > R(0);
+  return (pos ? R(-2) * C : sq - B) / (pos ? B + sq : R(2) * A);
 }
 
 // New velocity after a real collision: the old direction turned by
