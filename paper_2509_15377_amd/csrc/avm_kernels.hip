@@ -344,6 +344,10 @@ struct Xfer {
 // up to ~27 us; measured 8-12 % faster than one short nap on the
 // 1000-avalanche benchmark, where most waves are idle while the avalanches
 // start and end).
+// Waves carrying electrons issue ahead of waves that only poll the queue.
+#ifndef AVM_BUSY_PRIO
+#define AVM_BUSY_PRIO 1
+#endif
 #ifndef AVM_IDLE_NAP
 #define AVM_IDLE_NAP 16
 #endif
@@ -573,9 +577,15 @@ __global__ void __launch_bounds__(kPBlock)
       // nothing to carry: leave the SIMD to busy waves for a while before
       // polling the queue again (the polls and the exchange code would
       // otherwise take their issue slots)
+#if AVM_BUSY_PRIO
+      __builtin_amdgcn_s_setprio(0);
+#endif
       idle_naps = idle_naps < AVM_IDLE_MAX_NAPS ? 2 * idle_naps + 1 : AVM_IDLE_MAX_NAPS;
       for (int i = 0; i < idle_naps; ++i) __builtin_amdgcn_s_sleep(AVM_IDLE_NAP);
     } else {
+#if AVM_BUSY_PRIO
+      __builtin_amdgcn_s_setprio(2);
+#endif
       idle_naps = 0;
     }
   }
