@@ -560,13 +560,14 @@ AVM_FN uint32_t slab_exit(double z0, double vz, double az, double zlo, double zh
 // rotated to Cartesian.
 template <class R>
 AVM_FN void polar_field(const FieldDev& F, double x, double y, R& Ex, R& Ey) {
-  const double rho = sqrt_nn(x * x + y * y);
-  if (!(rho > 0.0)) {
+  const double r2 = x * x + y * y;
+  if (!(r2 > 0.0)) {
     Ex = R(0);
     Ey = R(0);
     return;
   }
-  double u = (log(rho) - F.ln_a) * F.inv_dlog;
+  // ln rho = ln(rho^2) / 2, and 1/rho from one reciprocal square root
+  double u = (0.5 * log_pos(r2) - F.ln_a) * F.inv_dlog;
   const double umax = (double)(F.n_r - 1);
   u = u < 0.0 ? 0.0 : (u > umax ? umax : u);
   int i = (int)floor(u);
@@ -589,7 +590,7 @@ AVM_FN void polar_field(const FieldDev& F, double x, double y, R& Ex, R& Ey) {
                w11 * (R)A[(i + 1) * np + j1];
   const R ep = w00 * (R)B[i * np + j0] + w01 * (R)B[i * np + j1] + w10 * (R)B[(i + 1) * np + j0] +
                w11 * (R)B[(i + 1) * np + j1];
-  const double inv = 1.0 / rho;
+  const double inv = rsqrt_pos(r2);
   const R c = (R)(x * inv), s = (R)(y * inv);
   Ex = er * c - ep * s;
   Ey = er * s + ep * c;
