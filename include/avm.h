@@ -42,7 +42,7 @@ typedef enum {
   AVM_E_NOMEM = 2,       /* host or device allocation failed                        */
   AVM_E_HIP = 3,         /* a HIP runtime call failed (message carries its text)    */
   AVM_E_CAPACITY = 4,    /* run finished but electrons beyond capacity were dropped */
-  AVM_E_UNSUPPORTED = 5, /* valid request this build does not implement             */
+  AVM_E_UNSUPPORTED = 5, /* valid request this library does not implement           */
   AVM_E_TIMEOUT = 6,     /* the run did not finish within the requested wall time   */
   AVM_E_STATE = 7        /* call out of order (e.g. results before a run)           */
 } avm_status;
