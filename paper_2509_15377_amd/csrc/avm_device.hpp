@@ -702,10 +702,21 @@ AVM_FN ChanP<R> chan(const GasDev& G, const TabLds<R>& T, int32_t c) {
 
 template <class R, class TV>
 AVM_FN int32_t band_of(const GasDev& G, const TV& T, R e) {
+  const int32_t nb = G.n_bands;
   int32_t b = (int32_t)(e * Sel<R>::band_scale(G));
-  b = b < 0 ? 0 : (b > G.n_bands - 1 ? G.n_bands - 1 : b);
-  while (b < G.n_bands - 1 && !(e < band_edge(G, T, b))) ++b;
-  while (b > 0 && e < band_edge(G, T, b - 1)) --b;
+  b = b < 0 ? 0 : (b > nb - 1 ? nb - 1 : b);
+  // the first guess is the band or a neighbour: both of its edges are read
+  // at once (the last band's edge is infinite), and the rare further steps
+  // follow one at a time
+  const R hi = band_edge(G, T, b);
+  const R lo = band_edge(G, T, b > 0 ? b - 1 : 0);
+  if (b < nb - 1 && !(e < hi)) {
+    ++b;
+    while (b < nb - 1 && !(e < band_edge(G, T, b))) ++b;
+  } else if (b > 0 && e < lo) {
+    --b;
+    while (b > 0 && e < band_edge(G, T, b - 1)) --b;
+  }
   return b;
 }
 
@@ -1072,11 +1083,17 @@ AVM_FN int32_t flight_step(Elec<R>& e, const GasDev& G, const TV& T, const Field
   HelixBound hb{};
   if (helical)
     hb = helix_bound(F, P, (double)e.vx, (double)e.vy, (double)e.vz, (double)Ex, (double)Ey, (double)Ez);
+  // the current band's tables are read first, and the logarithm (which does
+  // not depend on the band) is formed while they arrive
+  const int32_t band0 = e.band;
+  const R gam0 = kBanded ? band_gamma(G, T, band0) : Sel<R>::gamma(G);
+  const R inv0 = kBanded ? band_inv(G, T, band0) : Sel<R>::inv_gamma(G);
+  const R nlog = -Mr::log_(u1);
   if (kBanded && P.look > 0.0 && e.band < G.n_bands - 1) {
     // lookahead: raise the band to the band of the energy after `look` mean
     // free times of the current band (the flight energy, or its helical
     // bound); the choice uses only the state at the flight start
-    const double s_look = P.look * (double)band_inv(G, T, e.band);
+    const double s_look = P.look * (double)inv0;
     R e_look;
     if (helical) {
       const double vpar = hb.vp + hb.ap * s_look;
@@ -1094,9 +1111,12 @@ AVM_FN int32_t flight_step(Elec<R>& e, const GasDev& G, const TV& T, const Field
   if (helical)
     while (e.band < G.n_bands - 1 && (hb.vp * hb.vp + hb.p * hb.p) * P.inv_2ka >= (double)band_edge(G, T, e.band))
       e.band += 1;
-  const R gam = kBanded ? band_gamma(G, T, e.band) : Sel<R>::gamma(G);
-  const R inv_gam = kBanded ? band_inv(G, T, e.band) : Sel<R>::inv_gamma(G);
-  const R tau = -Mr::log_(u1) * inv_gam;
+  R gam = gam0, inv_gam = inv0;
+  if (kBanded && e.band != band0) {
+    gam = band_gamma(G, T, e.band);
+    inv_gam = band_inv(G, T, e.band);
+  }
+  const R tau = nlog * inv_gam;
   R tau_end = tau;
   int cut = 0;  // 1: band edge, 2: time limit
   if (helical) {
