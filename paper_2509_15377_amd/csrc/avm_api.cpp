@@ -1122,6 +1122,11 @@ hipError_t tune_key(const avm_gas* g, const avm_field* fl, const avm_primary* pr
   return e;
 }
 
+// Version of the cache lines: raised whenever the transport kernel changes
+// enough that an earlier timing no longer ranks the candidates right, so
+// that lines from an older library are ignored (and a new choice appended).
+constexpr int kTuneLineVersion = 3;
+
 bool cache_lookup(const char* path, uint64_t key, int* fpp, int* wpc, int* bb, float* look, double* ms) {
   if (!path) return false;
   std::FILE* fp = std::fopen(path, "r");
@@ -1131,9 +1136,11 @@ bool cache_lookup(const char* path, uint64_t key, int* fpp, int* wpc, int* bb, f
   while (std::fgets(line, sizeof line, fp)) {
     unsigned long long k = 0;
     int a = 0, b = 0, c = 0;
+    int v = 0;
     float l = 0.0f;
     double t = 0.0;
-    if (std::sscanf(line, "avm_tune 2 %llx %d %d %d %f %lf", &k, &a, &b, &c, &l, &t) == 6 && k == key) {
+    if (std::sscanf(line, "avm_tune %d %llx %d %d %d %f %lf", &v, &k, &a, &b, &c, &l, &t) == 7 &&
+        v == kTuneLineVersion && k == key) {
       *fpp = a; *wpc = b; *bb = c; *look = l; *ms = t;
       found = true;  // the last matching line wins
     }
@@ -1277,8 +1284,8 @@ extern "C" avm_status avm_autotune(avm_gas* gas, const avm_field* field, const a
   if (cache_path) {
     std::FILE* fp = std::fopen(cache_path, "a");
     if (!fp) return fail(AVM_E_ARG, "avm_autotune: cannot append to %s", cache_path);
-    std::fprintf(fp, "avm_tune 2 %016llx %d %d %d %.3f %.6f\n", (unsigned long long)key, best.fpp,
-                 best.wpc, best.bb, (double)best.look, best.ms);
+    std::fprintf(fp, "avm_tune %d %016llx %d %d %d %.3f %.6f\n", kTuneLineVersion,
+                 (unsigned long long)key, best.fpp, best.wpc, best.bb, (double)best.look, best.ms);
     std::fclose(fp);
   }
   return AVM_OK;
