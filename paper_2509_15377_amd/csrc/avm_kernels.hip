@@ -436,18 +436,22 @@ __global__ void __launch_bounds__(kPBlock)
       break;
     }
     // ---- transport pass
-    uint32_t term = 0;  // this lane's electron terminated in this pass
+    uint32_t term = 0;  // status of this lane's electron if it terminated in this pass
     for (int f = 0; f < flights_per_pass && has && !cp; ++f) {
       uint32_t status = 0;
       const int32_t r = flight_step<R, kBanded, kField, kSignal>(e, G, T, F, P, child, status, &Q);
       if (r == STEP_IONISED) {
         cp = true;
       } else if (r == STEP_DONE) {
-        if (kSignal) signal_end<R, kField>(Q, e);
-        write_end<R>(pinned(Sg), slot, e, P, status);
         has = false;
-        term = 1;
+        term = status;
       }
+    }
+    // ---- endpoints of this pass, written together (the state of a
+    // terminated electron stays in place until the exchange)
+    if (term) {
+      if (kSignal) signal_end<R, kField>(Q, e);
+      write_end<R>(pinned(Sg), slot, e, P, term);
     }
     // ---- ionisations of this pass, finished together
     if (cp) {
