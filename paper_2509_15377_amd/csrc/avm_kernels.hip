@@ -363,8 +363,9 @@ struct Xfer {
 
 // Every lane carries one electron at a time through up to `flights_per_pass`
 // flights; a lane stops early when its electron ends or ionises (the
-// secondary waits in registers).  At the end of a pass the wave, in
-// lockstep:
+// secondary waits in registers).  After the flights, the lanes whose
+// electron ended write their endpoint records together, and the lanes that
+// ionised finish their collisions together.  Then the wave, in lockstep:
 //   1. allocates storage slots for its new secondaries (one atomic on
 //      `tail`, which so counts every electron created, before any of them
 //      can be seen by another wave);
