@@ -138,6 +138,10 @@ struct TabLds {
   const AVM_LDS R* binv;
   const AVM_LDS R* bedge;
   const AVM_LDS ChanP<R>* ch;
+  // every band and channel is staged: the same for all lanes, so the
+  // accessors test it with a scalar branch and skip the per-lane index
+  // test (and its divergent global path) altogether
+  bool fit;
 };
 
 enum FieldKind : int32_t { FIELD_SLAB = 0, FIELD_POLAR = 1 };
@@ -684,19 +688,22 @@ template <class R>
 AVM_FN ChanP<R> chan(const GasDev&, const TabView<R>& T, int32_t c) { return T.ch[c]; }
 template <class R>
 AVM_FN R band_gamma(const GasDev& G, const TabLds<R>& T, int32_t b) {
+  if (T.fit) return T.bgam[b];
   return b < kLdsBands ? T.bgam[b] : Sel<R>::bgam(pinned(&G))[b];
 }
 template <class R>
 AVM_FN R band_inv(const GasDev& G, const TabLds<R>& T, int32_t b) {
+  if (T.fit) return T.binv[b];
   return b < kLdsBands ? T.binv[b] : Sel<R>::binv(pinned(&G))[b];
 }
 template <class R>
 AVM_FN R band_edge(const GasDev& G, const TabLds<R>& T, int32_t b) {
+  if (T.fit) return T.bedge[b];
   return b < kLdsBands ? T.bedge[b] : Sel<R>::bedge(pinned(&G))[b];
 }
 template <class R>
 AVM_FN ChanP<R> chan(const GasDev& G, const TabLds<R>& T, int32_t c) {
-  if (c < kLdsChannels) return T.ch[c];
+  if (T.fit || c < kLdsChannels) return T.ch[c];
   return Sel<R>::ch(pinned(&G))[c];
 }
 

@@ -418,7 +418,8 @@ __global__ void __launch_bounds__(kPBlock)
   if ((int)threadIdx.x < n_lc) s_ch[threadIdx.x] = Tg.ch[threadIdx.x];
   __syncthreads();
   const TabLds<R> T{(const AVM_LDS R*)s_tot, (const AVM_LDS R*)s_cum0, n_lo, (const AVM_LDS R*)s_bg,
-                    (const AVM_LDS R*)s_bi, (const AVM_LDS R*)s_be, (const AVM_LDS ChanP<R>*)s_ch};
+                    (const AVM_LDS R*)s_bi, (const AVM_LDS R*)s_be, (const AVM_LDS ChanP<R>*)s_ch,
+                    G.n_bands <= kLdsBands && G.n_ch <= kLdsChannels};
   Xfer& X = xfer_all[threadIdx.x >> 6];
   const uint32_t lane = __lane_id();
   bool has = false, cp = false;
