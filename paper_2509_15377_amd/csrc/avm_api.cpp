@@ -613,7 +613,8 @@ static size_t layout_store(Store& S, char* base, uint64_t cap) {
 static hipError_t batched_grid(const avm_run* r, int32_t waves_per_cu, int* grid, int* blocks_per_cu_max) {
   int per_cu = 0, n_cu = 0, dev = 0;
   hipError_t e = persistent_occupancy(r->opts.precision == AVM_FP32_MIXED, r->opts.majorant == AVM_MAJORANT_BANDED,
-                                      r->field->dev.kind, r->signal != nullptr, r->block, &per_cu);
+                                      r->field->dev.kind, r->signal != nullptr, tables_fit_lds(r->gas->dev),
+                                      r->block, &per_cu);
   if (e == hipSuccess) e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) return e;

@@ -120,6 +120,10 @@ struct TabView {
 constexpr int kLdsBands = 512;    // band tables staged in LDS (the first this many)
 constexpr int kLdsChannels = 64;  // channel parameters staged in LDS (the first this many)
 
+// Every band and channel of the gas fits the LDS copies (host side: selects
+// the persistent kernel's kFit instance).
+inline bool tables_fit_lds(const GasDev& G) { return G.n_bands <= kLdsBands && G.n_ch <= kLdsChannels; }
+
 // Pointers into LDS, typed as such in device code: loads through them are
 // DS instructions (a pointer that may hold either an LDS or a global address
 // is read with the slower FLAT instructions).
@@ -138,10 +142,22 @@ struct TabLds {
   const AVM_LDS R* binv;
   const AVM_LDS R* bedge;
   const AVM_LDS ChanP<R>* ch;
-  // every band and channel is staged: the same for all lanes, so the
-  // accessors test it with a scalar branch and skip the per-lane index
-  // test (and its divergent global path) altogether
-  bool fit;
+};
+
+// The same LDS copies when every band and channel is staged (the persistent
+// kernel's kFit instances): the accessors read them without an index test.
+// With the per-lane test each read carries a divergent global path, and the
+// waits the compiler places where the two paths join also hold up the LDS
+// reads that follow.
+template <class R>
+struct TabFit {
+  const AVM_LDS R* tot;
+  const AVM_LDS R* cum0;
+  int32_t n_lo;
+  const AVM_LDS R* bgam;
+  const AVM_LDS R* binv;
+  const AVM_LDS R* bedge;
+  const AVM_LDS ChanP<R>* ch;
 };
 
 enum FieldKind : int32_t { FIELD_SLAB = 0, FIELD_POLAR = 1 };
@@ -688,24 +704,29 @@ template <class R>
 AVM_FN ChanP<R> chan(const GasDev&, const TabView<R>& T, int32_t c) { return T.ch[c]; }
 template <class R>
 AVM_FN R band_gamma(const GasDev& G, const TabLds<R>& T, int32_t b) {
-  if (T.fit) return T.bgam[b];
   return b < kLdsBands ? T.bgam[b] : Sel<R>::bgam(pinned(&G))[b];
 }
 template <class R>
 AVM_FN R band_inv(const GasDev& G, const TabLds<R>& T, int32_t b) {
-  if (T.fit) return T.binv[b];
   return b < kLdsBands ? T.binv[b] : Sel<R>::binv(pinned(&G))[b];
 }
 template <class R>
 AVM_FN R band_edge(const GasDev& G, const TabLds<R>& T, int32_t b) {
-  if (T.fit) return T.bedge[b];
   return b < kLdsBands ? T.bedge[b] : Sel<R>::bedge(pinned(&G))[b];
 }
 template <class R>
 AVM_FN ChanP<R> chan(const GasDev& G, const TabLds<R>& T, int32_t c) {
-  if (T.fit || c < kLdsChannels) return T.ch[c];
+  if (c < kLdsChannels) return T.ch[c];
   return Sel<R>::ch(pinned(&G))[c];
 }
+template <class R>
+AVM_FN R band_gamma(const GasDev&, const TabFit<R>& T, int32_t b) { return T.bgam[b]; }
+template <class R>
+AVM_FN R band_inv(const GasDev&, const TabFit<R>& T, int32_t b) { return T.binv[b]; }
+template <class R>
+AVM_FN R band_edge(const GasDev&, const TabFit<R>& T, int32_t b) { return T.bedge[b]; }
+template <class R>
+AVM_FN ChanP<R> chan(const GasDev&, const TabFit<R>& T, int32_t c) { return T.ch[c]; }
 
 template <class R, class TV>
 AVM_FN int32_t band_of(const GasDev& G, const TV& T, R e) {

@@ -86,7 +86,7 @@ hipError_t launch_persistent(int fp32, int banded, int field_kind, const GasDev&
                              hipStream_t st);
 hipError_t launch_zero(double* p, size_t n, hipStream_t st);
 int persistent_block();  // threads per block of the persistent kernel
-hipError_t persistent_occupancy(int fp32, int banded, int field_kind, int signal, int block,
+hipError_t persistent_occupancy(int fp32, int banded, int field_kind, int signal, int fit, int block,
                                 int* blocks_per_cu);
 hipError_t launch_tables_f32(const double* cum, const double* total, const double* cum0,
                              size_t n_cum, int n_nodes, const double* bg, const double* be,

@@ -385,8 +385,9 @@ struct Xfer {
 // leaves.
 //
 // kSignal: the electrons also deposit their induced signal (Shockley-Ramo,
-// binned in time) on the readout electrode.
-template <class R, bool kBanded, int kField, bool kSignal>
+// binned in time) on the readout electrode.  kFit: every band and channel
+// fits the LDS copies, and the flights read them without index tests.
+template <class R, bool kBanded, int kField, bool kSignal, bool kFit>
 __global__ void __launch_bounds__(kPBlock)
     __attribute__((amdgpu_waves_per_eu(AVM_PERSISTENT_WAVES_PER_EU, AVM_PERSISTENT_WAVES_PER_EU)))
     k_persistent(GasDev G, FieldDev F, RunParams P, const Store* __restrict__ Sg, Counters* ctr,
@@ -417,9 +418,9 @@ __global__ void __launch_bounds__(kPBlock)
   const int n_lc = G.n_ch < kLdsChannels ? G.n_ch : kLdsChannels;
   if ((int)threadIdx.x < n_lc) s_ch[threadIdx.x] = Tg.ch[threadIdx.x];
   __syncthreads();
-  const TabLds<R> T{(const AVM_LDS R*)s_tot, (const AVM_LDS R*)s_cum0, n_lo, (const AVM_LDS R*)s_bg,
-                    (const AVM_LDS R*)s_bi, (const AVM_LDS R*)s_be, (const AVM_LDS ChanP<R>*)s_ch,
-                    G.n_bands <= kLdsBands && G.n_ch <= kLdsChannels};
+  using View = std::conditional_t<kFit, TabFit<R>, TabLds<R>>;
+  const View T{(const AVM_LDS R*)s_tot, (const AVM_LDS R*)s_cum0, n_lo, (const AVM_LDS R*)s_bg,
+               (const AVM_LDS R*)s_bi, (const AVM_LDS R*)s_be, (const AVM_LDS ChanP<R>*)s_ch};
   Xfer& X = xfer_all[threadIdx.x >> 6];
   const uint32_t lane = __lane_id();
   bool has = false, cp = false;
@@ -714,27 +715,34 @@ hipError_t launch_generation(int fp32, int banded, int field_kind, const GasDev&
   return hipGetLastError();
 }
 
-template <class R, bool SIG>
-static const void* pick_persistent_sig(int banded, int fk) {
+template <class R, bool SIG, bool FIT>
+static const void* pick_persistent_fit(int banded, int fk) {
   if (banded)
-    return fk == FIELD_SLAB ? reinterpret_cast<const void*>(&k_persistent<R, true, FIELD_SLAB, SIG>)
-                            : reinterpret_cast<const void*>(&k_persistent<R, true, FIELD_POLAR, SIG>);
-  return fk == FIELD_SLAB ? reinterpret_cast<const void*>(&k_persistent<R, false, FIELD_SLAB, SIG>)
-                          : reinterpret_cast<const void*>(&k_persistent<R, false, FIELD_POLAR, SIG>);
+    return fk == FIELD_SLAB ? reinterpret_cast<const void*>(&k_persistent<R, true, FIELD_SLAB, SIG, FIT>)
+                            : reinterpret_cast<const void*>(&k_persistent<R, true, FIELD_POLAR, SIG, FIT>);
+  return fk == FIELD_SLAB ? reinterpret_cast<const void*>(&k_persistent<R, false, FIELD_SLAB, SIG, FIT>)
+                          : reinterpret_cast<const void*>(&k_persistent<R, false, FIELD_POLAR, SIG, FIT>);
 }
 
-static const void* pick_persistent(int fp32, int banded, int fk, int signal) {
+template <class R, bool SIG>
+static const void* pick_persistent_sig(int banded, int fk, int fit) {
+  return fit ? pick_persistent_fit<R, SIG, true>(banded, fk) : pick_persistent_fit<R, SIG, false>(banded, fk);
+}
+
+static const void* pick_persistent(int fp32, int banded, int fk, int signal, int fit) {
   if (fp32)
-    return signal ? pick_persistent_sig<float, true>(banded, fk) : pick_persistent_sig<float, false>(banded, fk);
-  return signal ? pick_persistent_sig<double, true>(banded, fk) : pick_persistent_sig<double, false>(banded, fk);
+    return signal ? pick_persistent_sig<float, true>(banded, fk, fit)
+                  : pick_persistent_sig<float, false>(banded, fk, fit);
+  return signal ? pick_persistent_sig<double, true>(banded, fk, fit)
+                : pick_persistent_sig<double, false>(banded, fk, fit);
 }
 
 int persistent_block() { return kPBlock; }
 
-hipError_t persistent_occupancy(int fp32, int banded, int field_kind, int signal, int block,
+hipError_t persistent_occupancy(int fp32, int banded, int field_kind, int signal, int fit, int block,
                                 int* blocks_per_cu) {
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(
-      blocks_per_cu, pick_persistent(fp32, banded, field_kind, signal), block, 0);
+      blocks_per_cu, pick_persistent(fp32, banded, field_kind, signal, fit), block, 0);
 }
 
 hipError_t launch_persistent(int fp32, int banded, int field_kind, const GasDev& G,
@@ -743,7 +751,7 @@ hipError_t launch_persistent(int fp32, int banded, int field_kind, const GasDev&
                              hipStream_t st) {
   SignalDev Q{};
   if (signal) Q = *signal;
-  const void* fn = pick_persistent(fp32, banded, field_kind, signal != nullptr);
+  const void* fn = pick_persistent(fp32, banded, field_kind, signal != nullptr, tables_fit_lds(G));
   void* args[] = {const_cast<GasDev*>(&G), const_cast<FieldDev*>(&F), const_cast<RunParams*>(&P),
                   const_cast<Store**>(&S), &ctr, &flights_per_pass, &Q};
   return hipLaunchKernel(fn, dim3(grid), dim3(block), args, 0, st);
