@@ -235,3 +235,39 @@ def test_graph_replays_match_eager(A):
             eager.execute(); eager.sync()  # eager work between replays
         gr.close()
         eager.close()
+
+
+def _many_channel_gas():
+    """The argon-like gas with every excitation split into three channels
+    of a third of its cross section: 92 channels, so the parameters of the
+    channels past the 64 staged in LDS (the upper excitations and the
+    ionisation) are read from global memory."""
+    import dataclasses
+    gas = W.argon_like_gas()
+    chans = [gas.channels[0]]
+    for ch in gas.channels[1:-1]:
+        chans += [dataclasses.replace(ch, values=ch.values / 3.0) for _ in range(3)]
+    chans.append(gas.channels[-1])
+    return dataclasses.replace(gas, channels=chans)
+
+
+@pytest.mark.parametrize("case", ["bands", "channels"])
+def test_tables_beyond_the_lds_copies(A, oracle_mod, case):
+    """Gases whose tables do not all fit the persistent kernel's LDS copies
+    (more than 512 bands, or more than 64 channels) run the kernel instance
+    that tests each index and reads the rest from global memory."""
+    wl = W.argon()
+    prim = _sub(wl, 24)
+    if case == "bands":
+        gas, bb = wl.gas, 20  # 1000 bands
+    else:
+        gas, bb = _many_channel_gas(), 100
+    g = A.Gas(gas, band_bins=bb)
+    assert (g.n_bands > 512) if case == "bands" else (len(gas.channels) > 64)
+    ref = oracle_mod.run(oracle_mod.Gas(gas, band_bins=bb), wl.field, prim, wl.seed, banded=True,
+                         band_lookahead=1.0)
+    ep, tot, _ = A.run(gas=g, field=A.Field(wl.field), primaries=prim, n_aval=24, seed=wl.seed,
+                       majorant=A.BANDED, band_lookahead=1.0, capacity=4_000_000)
+    rep = CMP.assert_parity(ep, ref)
+    print("beyond LDS", case, rep)
+    assert tot["n_ion"] > 0
