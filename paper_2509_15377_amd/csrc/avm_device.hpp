@@ -748,9 +748,11 @@ AVM_FN int32_t band_of(const GasDev& G, const TV& T, R e) {
   return b;
 }
 
-template <class R>
+// Termination status of a position outside the drift region, 0 inside
+// (the geometry is the kernel's kField, the same as F.kind).
+template <class R, int kField>
 AVM_FN uint32_t region_status(const FieldDev& F, const Elec<R>& e) {
-  if (F.kind == FIELD_SLAB) {
+  if (kField == FIELD_SLAB) {
     if (e.z < F.z_lo) return ST_LOW;
     if (e.z >= F.z_hi) return ST_HIGH;
     return 0;
@@ -1088,7 +1090,7 @@ AVM_FN int32_t flight_step(Elec<R>& e, const GasDev& G, const TV& T, const Field
   using Mr = M<R>;
   constexpr bool kMixed = sizeof(R) == 4;
   // position valid, flights and time left?
-  uint32_t st0 = region_status<R>(F, e);
+  uint32_t st0 = region_status<R, kField>(F, e);
   st0 = st0 ? st0 : (e.k >= P.k_max ? (uint32_t)ST_ABANDONED : (e.t >= P.t_max ? (uint32_t)ST_TIME : 0u));
   if (st0) {
     status = st0;
