@@ -108,3 +108,22 @@ def test_mixed_batched_equals_plain(A):
     b, tb, _ = A.run(wl, precision=A.FP32_MIXED, mode=A.BATCHED, capacity=100000, timeout_s=60.0)
     assert a.tobytes() == b.tobytes()
     assert ta == tb
+
+
+def test_mixed_tables_beyond_the_lds_copies(A):
+    """FP32-mixed with 1000 bands (more than the 512 staged in LDS: the
+    kernel instance with index tests) against FP64 at the same band width
+    (itself matched to the oracle per trajectory in test_gpu_parity.py),
+    paired by avalanche."""
+    wl = W.argon(400, band_bins=20)
+    e64, t64, p64 = _run(A, wl, A.FP64)
+    e32, t32, p32 = _run(A, wl, A.FP32_MIXED)
+    assert t32["n_endpoints"] == e32.size == wl.n_aval + t32["n_ion"]
+    assert t32["n_band"] > 0 and t32["truncated"] == 0
+    g64 = p64["n_endpoints"].astype(float)
+    g32 = p32["n_endpoints"].astype(float)
+    rel = abs(g32.mean() - g64.mean()) / g64.mean()
+    corr = np.corrcoef(g64, g32)[0, 1]
+    print(f"1000 bands: mean gain fp64 {g64.mean():.2f} fp32 {g32.mean():.2f} rel {rel:.2e} corr {corr:.3f}")
+    assert rel < 0.02
+    assert stats.ks_2samp(e64["t1"], e32["t1"]).pvalue > 1e-3
