@@ -34,7 +34,7 @@
 extern "C" {
 #endif
 
-#define AVM_ABI_VERSION 1
+#define AVM_ABI_VERSION 2
 
 typedef enum {
   AVM_OK = 0,
@@ -194,15 +194,24 @@ typedef struct {
                           /*   the restart rule keeps sampling exact; 0: none; >= 0      */
 } avm_run_opts;
 
-/* One electron's record.  status: 1 left z_lo, 2 left z_hi, 3 attached,
- * 4 hit the wire, 5 reached the tube, 6 time limit, 7 flight limit,
- * 8 numerical error.  eid: primaries 2^63 | index, secondaries 63-bit ids
- * drawn from the parent's random stream; parent = 0 for primaries. */
+/* One electron's record (the endpoint getter of paper Sec. 3.2: start and
+ * end position, time and energy, status).  status: 1 left z_lo, 2 left
+ * z_hi, 3 attached, 4 hit the wire, 5 reached the tube, 6 time limit,
+ * 7 flight limit, 8 numerical error.  eid: primaries 2^63 | index,
+ * secondaries 63-bit ids drawn from the parent's random stream; parent = 0
+ * for primaries.  trace: the electron's decision trace, a running 32-bit
+ * hash over its real collisions, masked nulls and band cuts in flight
+ * order -- from 0, each such event at flight index k maps h to
+ * rotl(h, 5) ^ (k 2^18 + code), code = c for a real collision in channel c,
+ * 2^16 + c for a masked null at channel c, 2^17 for a band cut -- so that
+ * runs can be compared decision by decision (null collisions enter through
+ * n_null). */
 typedef struct {
   double x0, y0, z0, t0, e0, x1, y1, z1, t1, e1;
   uint64_t eid, parent;
   uint32_t avalanche, status, n_real, n_ion, n_null, n_masked, n_band, n_overflow;
-} avm_endpoint; /* 128 bytes */
+  uint32_t trace, _pad;
+} avm_endpoint; /* 136 bytes */
 
 /* Counters of a run (or of a range of avalanches).  gain of avalanche a =
  * n_endpoints / number of its primaries. */
@@ -253,6 +262,7 @@ typedef struct {
   const double *x0, *y0, *z0, *t0, *e0, *x1, *y1, *z1, *t1, *e1;
   const uint64_t *eid, *parent;
   const uint32_t *avalanche, *status, *n_real, *n_ion, *n_null, *n_masked, *n_band, *n_overflow;
+  const uint32_t* trace;
 } avm_endpoint_arrays;
 avm_status avm_run_endpoint_arrays(const avm_run* run, avm_endpoint_arrays* out);
 

@@ -437,6 +437,11 @@ int orc_field_eval(const orc_field* f, const double r[3], uint32_t aval, double 
   double fp = w - wf;
   int32_t j0 = ((int32_t)wf) % f->n_phi;
   int32_t j1 = (j0 + 1) % f->n_phi;
+#if defined(ORC_PLANT_PHI_SWAP)
+  { int32_t tmp = j0; j0 = j1; j1 = tmp; }
+#elif defined(ORC_PLANT_PHI_WRAP)
+  j1 = j0 + 1 < f->n_phi ? j0 + 1 : j0;
+#endif
   const float* ER = f->Er;
   const float* EP = f->Ephi;
   int32_t np = f->n_phi;
@@ -445,7 +450,11 @@ int orc_field_eval(const orc_field* f, const double r[3], uint32_t aval, double 
   double ep = (1.0 - fr) * (1.0 - fp) * (double)EP[i * np + j0] + (1.0 - fr) * fp * (double)EP[i * np + j1] +
               fr * (1.0 - fp) * (double)EP[(i + 1) * np + j0] + fr * fp * (double)EP[(i + 1) * np + j1];
   double c = r[0] / rho, s = r[1] / rho;
+#if defined(ORC_PLANT_EPHI_SIGN)
+  E[0] = er * c + ep * s;
+#else
   E[0] = er * c - ep * s;
+#endif
   E[1] = er * s + ep * c;
   E[2] = 0.0;
   return ORC_OK;
@@ -809,6 +818,14 @@ static void signal_flight(const ctx_t* cx, uint32_t aval, const double r_s[3], c
 
 static double energy_of(const double v[3]) { return dot3(v, v) / (2.0 * orc_k_a()); }
 
+/* One event of the decision trace (see orc_endpoint): rotate left by 5,
+ * then mix in the flight index and the event code. */
+static uint32_t trace_step(uint32_t h, uint32_t k, uint32_t code)
+{
+  return ((h << 5) | (h >> 27)) ^ ((k << 18) + code);
+}
+enum { TRACE_MASKED = 1u << 16, TRACE_BAND = 1u << 17 };
+
 /* Decisions that saw an interpolated total rate above the majorant in use
  * (a majorant that is not one; counted for the pins, never expected). */
 static uint64_t g_majorant_violations = 0;
@@ -861,9 +878,10 @@ static int push_secondary(estack* st, const elec* parent, double e_s, double uC,
 }
 
 /* Carry one electron through the loop of Fig. 2 until it terminates.  Each
- * pass: position valid? -> field at r, random flight time -> boundary, time
- * limit or band edge within the flight? -> collision? (real or null) ->
- * scattering; ionisation pushes the secondary onto `st`. */
+ * pass checks the position, takes the field at r and a random flight time,
+ * looks for a boundary, the time limit or a band edge within the flight,
+ * decides between a real and a null collision and scatters; an ionisation
+ * pushes the secondary onto `st`. */
 static int transport(const ctx_t* cx, elec e, estack* st, orc_endpoint* ep)
 {
   const orc_gas* g = cx->g;
@@ -885,7 +903,7 @@ static int transport(const ctx_t* cx, elec e, estack* st, orc_endpoint* ep)
   int32_t band = banded ? orc_gas_band_of(g, energy_of(e.v)) : g->n_bands - 1;
   int status = 0;
   for (;;) {
-    /* position valid? */
+    /* still inside the volume? */
     status = region_status(f, e.r);
     if (status) break;
     if (k >= o->k_max) {
@@ -1016,6 +1034,7 @@ static int transport(const ctx_t* cx, elec e, estack* st, orc_endpoint* ep)
        * rounded energy at the edge */
       band = band + 1;
       ep->n_band++;
+      ep->trace = trace_step(ep->trace, k, TRACE_BAND);
       k++;
       continue;
     }
@@ -1042,11 +1061,13 @@ static int transport(const ctx_t* cx, elec e, estack* st, orc_endpoint* ep)
     while (c < g->n_ch - 1 && !(r_sel < cum_at(g, kb, fb, over, c))) c++;
     if (en < g->e_lo[c] || en >= g->e_hi[c]) {
       ep->n_masked++;
+      ep->trace = trace_step(ep->trace, k, TRACE_MASKED + (uint32_t)c);
       k++;
       if (banded) band = orc_gas_band_of(g, en);
       continue;
     }
     ep->n_real++;
+    ep->trace = trace_step(ep->trace, k, (uint32_t)c);
     if (g->kind[c] == ORC_ATTACHMENT) {
       status = ORC_ST_ATTACHED;
       break;
@@ -1059,9 +1080,13 @@ static int transport(const ctx_t* cx, elec e, estack* st, orc_endpoint* ep)
     double phi = TWO_PI * uB;
     double e_new;
     if (g->kind[c] == ORC_ELASTIC) {
+#if defined(ORC_PLANT_SR_ISOTROPIC)
+      double cos_chi = 1.0 - 2.0 * uA;
+#else
       double cos_chi = g->angular[c] == ORC_SCREENED_RUTHERFORD
                            ? orc_cos_screened_rutherford(uA, en, g->screening[c])
                            : 1.0 - 2.0 * uA;
+#endif
       double cos_lab;
       orc_elastic(en, g->mass_ratio[c], cos_chi, &e_new, &cos_lab);
       orc_rotate(d, cos_lab, phi, dn);
@@ -1089,8 +1114,16 @@ static int transport(const ctx_t* cx, elec e, estack* st, orc_endpoint* ep)
       double uC = orc_u53(w2[2], w2[3]);
       double uP = orc_u53(w3[0], w3[1]);
       uint64_t child = (((uint64_t)w3[3] << 32) | (uint64_t)w3[2]) & 0x7FFFFFFFFFFFFFFFull;
+#if defined(ORC_PLANT_OB_AVAIL)
+      double e_s = orc_split_energy(g->split[c], uS, en, g->split_w[c]);
+#else
       double e_s = orc_split_energy(g->split[c], uS, e_avail, g->split_w[c]);
+#endif
+#if defined(ORC_PLANT_ION_KEEP)
+      e_new = e_avail;
+#else
       e_new = e_avail - e_s;
+#endif
       orc_rotate(d, 1.0 - 2.0 * uA, phi, dn);
       /* the secondary starts where the ionisation happened, isotropically */
       if (push_secondary(st, &e, e_s, uC, uP, child) != ORC_OK) return ORC_E_NOMEM;

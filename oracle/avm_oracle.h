@@ -7,11 +7,12 @@
  * leg of the benchmark may load it.  It shares no source, header, table or
  * constant with the HIP implementation.
  *
- * What it computes (paper Sec. 2 and Fig. 2, the AvalancheMicroscopic outline:
- * "position valid? -> find E field and add random time step -> collision? ->
- * ionisation or attachment? -> store", repeated until every electron has a
- * non-zero status; null-collision free flights after Skullerud, cited in
- * Sec. 1): every electron of every avalanche is transported flight by flight
+ * What it computes (paper Sec. 2 and its Fig. 2: each electron is checked
+ * for still being inside the volume, takes a random free flight in the local
+ * field, may collide, and on an ionisation or attachment changes the electron
+ * count, until every electron has a non-zero status; null-collision free
+ * flights after Skullerud, cited in Sec. 1): every electron of every
+ * avalanche is transported flight by flight
  * through a gas described by an energy-binned rate table with linear
  * interpolation between nodes, with a majorant rate Gamma >= nu(e) that turns
  * the flight law into "exponential with rate Gamma, real with probability
@@ -22,8 +23,16 @@
  *
  * Parity pins: every function here is pinned by a CPU test against a closed
  * form, an invariant, brute force or an independent library (rocRAND's
- * Philox for the generator).  Nothing here is "parity unpinned" except the
+ * Philox for the generator); the polar map's azimuthal interpolation,
+ * periodic wrap and E_phi rotation against a field with a closed form, the
+ * scattering samplers as the transport calls them against a brute-force
+ * integrator, the ionisation energy split against the energy balance of
+ * every single event.  Nothing here is "parity unpinned" except the
  * physical correctness of the synthetic gas models, which are definitions.
+ *
+ * Planted mistakes: compiled with one of the ORC_PLANT_* macros (only the
+ * pin tests do this, into a separate library) the oracle carries one known
+ * mistake, so that a test can show that its pin catches it.
  */
 #ifndef AVM_ORACLE_H
 #define AVM_ORACLE_H
@@ -97,11 +106,20 @@ typedef struct {
   uint32_t aval, _pad;
 } orc_primary; /* 72 bytes */
 
+/* trace: the electron's decision trace, a running 32-bit hash over its
+ * real collisions, masked nulls and band cuts, in flight order: starting
+ * from 0, each such event at flight index k maps h to
+ * rotl(h, 5) ^ (k * 2^18 + code) (mod 2^32), with code = c for a real
+ * collision in channel c, 2^16 + c for a masked null whose chosen channel
+ * is c, 2^17 for a band cut (channel indices below 2^16).  Two runs whose
+ * electron made the same decisions give the same trace; null collisions
+ * enter through n_null. */
 typedef struct {
   double x0, y0, z0, t0, e0, x1, y1, z1, t1, e1;
   uint64_t eid, parent;
   uint32_t aval, status, n_real, n_ion, n_null, n_masked, n_band, n_overflow;
-} orc_endpoint; /* 128 bytes */
+  uint32_t trace, _pad;
+} orc_endpoint; /* 136 bytes */
 
 typedef struct {
   uint64_t seed;

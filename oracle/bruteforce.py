@@ -14,8 +14,15 @@ tabulated model), and the channel is chosen in proportion to its rate.  The
 result converges to the exact transport as dt -> 0 (first order), which is
 what the null-collision method (Skullerud, cited in Sec. 1) samples exactly.
 
-Supported: slab fields along z, isotropic elastic scattering with recoil,
-excitation, ionisation with a uniform split, attachment.
+Supported: slab fields along z; elastic scattering with target recoil,
+isotropic or screened Rutherford (dsigma/dOmega ~ (1 - cos chi + 2 eta)^-2,
+eta = screening / (8 e), sampled by rejection from a 1/(1 - cos chi + 2 eta)
+envelope, not by the oracle's inverse CDF); excitation; ionisation with a
+uniform or an Opal-Beaty split (dsigma/de_s ~ 1/(1 + (e_s/w)^2) on
+[0, (e - I)/2], sampled by rejection from a uniform proposal); attachment.
+The total valid rate at the sub-step ends comes from one piecewise-linear
+table whose breakpoints are the nodes and both sides of every channel's
+window edge (exact for the masked, linearly interpolated model).
 """
 from __future__ import annotations
 
@@ -52,11 +59,56 @@ def _turn(rng, d, cos_t):
             + (s * np.sin(phi))[:, None] * e2)
 
 
+def _screened_rutherford(rng, eta):
+    """cos chi with density ~ (1 - cos chi + 2 eta)^-2 on [-1, 1]: x = 1 -
+    cos chi + 2 eta is drawn from the envelope ~ 1/x on [2 eta, 2 + 2 eta]
+    (x = 2 eta (1 + 1/eta)^U) and kept with probability 2 eta / x."""
+    out = np.empty(eta.size)
+    todo = np.arange(eta.size)
+    while todo.size:
+        et = eta[todo]
+        x = 2.0 * et * np.power(1.0 + 1.0 / et, rng.random(todo.size))
+        ok = rng.random(todo.size) * x < 2.0 * et
+        out[todo[ok]] = 1.0 + 2.0 * et[ok] - x[ok]
+        todo = todo[~ok]
+    return out
+
+
+def _opal_beaty(rng, avail, w):
+    """Secondary energy with density ~ 1/(1 + (e_s/w)^2) on [0, avail/2]:
+    uniform proposal, kept with probability 1/(1 + (e_s/w)^2)."""
+    out = np.empty(avail.size)
+    todo = np.arange(avail.size)
+    while todo.size:
+        es = 0.5 * avail[todo] * rng.random(todo.size)
+        ok = rng.random(todo.size) * (1.0 + (es / w[todo]) ** 2) < 1.0
+        out[todo[ok]] = es[ok]
+        todo = todo[~ok]
+    return out
+
+
+def _valid_rate_table(e_nodes, nu_nodes, e_lo, e_hi):
+    """Breakpoints and values of the total valid rate: linear between nodes,
+    stepping at the window edges (both sides of each edge are breakpoints,
+    the lower one the largest double below the edge)."""
+    pts = [e_nodes]
+    for lo, hi in zip(e_lo, e_hi):
+        for edge in (lo, hi):
+            if 0.0 < edge <= e_nodes[-1]:
+                pts.append(np.array([np.nextafter(edge, -np.inf), edge]))
+    xs = np.unique(np.concatenate(pts))
+    tot = np.zeros(xs.size)
+    for c in range(len(nu_nodes)):
+        valid = (xs >= e_lo[c]) & (xs < e_hi[c])
+        tot += np.where(valid, np.interp(xs, e_nodes, nu_nodes[c]), 0.0)
+    return xs, tot
+
+
 def simulate(gas, z_hi, E_z, n_aval, dt, rng, block=128, max_electrons=10 ** 7):
     """Avalanches from one electron at rest at z = 0 in the slab [0, z_hi)
     with field magnitude E_z accelerating towards +z.  Returns per-electron
     arrays (aval, z, t, e, status) with status 1 (z < 0), 2 (z >= z_hi) or
-    3 (attached).
+    3 (attached), and the birth energies of the secondaries (``sec_e``).
 
     The sub-steps of every active electron are evaluated ``block`` at a time
     (positions, energies and collision draws of sub-steps 1..block in closed
@@ -64,7 +116,7 @@ def simulate(gas, z_hi, E_z, n_aval, dt, rng, block=128, max_electrons=10 ** 7):
     the same discrete process as one sub-step at a time."""
     e_nodes = (np.arange(gas.n_bins + 1, dtype=np.float64) * gas.e_max_eV) / gas.n_bins
     speed = np.sqrt(2.0 * K_A * e_nodes)
-    nu_nodes, kinds, e_lo, e_hi, loss, mu = [], [], [], [], [], []
+    nu_nodes, kinds, e_lo, e_hi, loss, mu, ang, scr, split, sw = [], [], [], [], [], [], [], [], [], []
     for ch in gas.channels:
         if ch.values_kind == 1:
             nu_nodes.append(np.asarray(ch.values, dtype=np.float64))
@@ -75,18 +127,28 @@ def simulate(gas, z_hi, E_z, n_aval, dt, rng, block=128, max_electrons=10 ** 7):
         e_hi.append(ch.e_hi_eV)
         loss.append(ch.loss_eV)
         mu.append(ch.mass_ratio)
-        if ch.kind == ELASTIC and ch.angular != 0:
-            raise NotImplementedError("brute force: isotropic elastic only")
-        if ch.kind == IONISATION and ch.split != 0:
-            raise NotImplementedError("brute force: uniform split only")
+        ang.append(ch.angular)
+        scr.append(ch.screening_eV)
+        split.append(ch.split)
+        sw.append(ch.split_w_eV)
+        if getattr(ch, "penning_prob", 0.0):
+            raise NotImplementedError("brute force: no Penning transfer")
     kinds = np.asarray(kinds)
     loss = np.asarray(loss)
     mu = np.asarray(mu)
+    ang = np.asarray(ang)
+    scr = np.asarray(scr, dtype=np.float64)
+    split = np.asarray(split)
+    sw = np.asarray(sw, dtype=np.float64)
+    if any(h > e_nodes[-1] and np.isfinite(h) for h in e_hi):
+        raise NotImplementedError("brute force: window edges above the table")
+    xs_tab, tot_tab = _valid_rate_table(e_nodes, nu_nodes, e_lo, e_hi)
     nch = len(kinds)
     acc = K_A * E_z  # along +z
     s = dt * np.arange(1, block + 1, dtype=np.float64)  # sub-step ends
 
     def rates(e):
+        """Per-channel valid rates (only at collisions)."""
         nu = np.zeros(e.shape + (nch,))
         for c in range(nch):
             r = np.interp(e, e_nodes, nu_nodes[c])  # constant above the last node
@@ -98,6 +160,7 @@ def simulate(gas, z_hi, E_z, n_aval, dt, rng, block=128, max_electrons=10 ** 7):
     t = np.zeros(n_aval)
     aval = np.arange(n_aval)
     out = {k: [] for k in ("aval", "z", "t", "e", "status")}
+    sec_e = []
 
     def emit(sel, z, tt, e, st):
         out["aval"].append(aval[sel]); out["z"].append(z); out["t"].append(tt)
@@ -112,8 +175,7 @@ def simulate(gas, z_hi, E_z, n_aval, dt, rng, block=128, max_electrons=10 ** 7):
         vzj = vel[:, 2:3] + acc * s
         vperp2 = vel[:, 0:1] ** 2 + vel[:, 1:2] ** 2
         ej = 0.5 * (vperp2 + vzj * vzj) / K_A
-        nu = rates(ej)
-        p = -np.expm1(-nu.sum(axis=2) * dt)
+        p = -np.expm1(-np.interp(ej, xs_tab, tot_tab) * dt)
         coll = rng.random((n, block)) < p
         outj = (zj >= z_hi) | (zj < 0.0)
         big = block + 1
@@ -161,7 +223,7 @@ def simulate(gas, z_hi, E_z, n_aval, dt, rng, block=128, max_electrons=10 ** 7):
             vel[ci, 2] = vzj[ci, jj]
             t[ci] += S
             e_i = ej[ci, jj]
-            nu_i = nu[ci, jj, :]
+            nu_i = rates(e_i)
             cum = np.cumsum(nu_i, axis=1)
             pick = rng.random(ci.size) * cum[:, -1]
             ch = np.minimum((cum <= pick[:, None]).sum(axis=1), nch - 1)
@@ -175,6 +237,10 @@ def simulate(gas, z_hi, E_z, n_aval, dt, rng, block=128, max_electrons=10 ** 7):
             if np.any(m):
                 mu_i = mu[ch[m]]
                 cchi = rng.uniform(-1.0, 1.0, m.sum())
+                sr = ang[ch[m]] != 0
+                if np.any(sr):
+                    eta = scr[ch[m]][sr] / (8.0 * e_i[m][sr])
+                    cchi[sr] = _screened_rutherford(rng, eta)
                 v_in = np.sqrt(2 * K_A * e_i[m])
                 vcm = mu_i / (1 + mu_i) * v_in
                 urel = v_in / (1 + mu_i)
@@ -192,6 +258,10 @@ def simulate(gas, z_hi, E_z, n_aval, dt, rng, block=128, max_electrons=10 ** 7):
             if np.any(m):
                 avail = e_i[m] - loss[ch[m]]
                 es = rng.random(m.sum()) * avail
+                ob = split[ch[m]] != 0
+                if np.any(ob):
+                    es[ob] = _opal_beaty(rng, avail[ob], sw[ch[m]][ob])
+                sec_e.append(es.copy())
                 new_e[m] = avail - es
                 new_d[m] = _iso_dirs(rng, m.sum())
                 sv = np.sqrt(2 * K_A * es)[:, None] * _iso_dirs(rng, m.sum())
@@ -210,4 +280,6 @@ def simulate(gas, z_hi, E_z, n_aval, dt, rng, block=128, max_electrons=10 ** 7):
             t = np.concatenate([t, sec[2]])
             aval = np.concatenate([aval, sec[3]])
 
-    return {k: np.concatenate(v) if v else np.zeros(0) for k, v in out.items()}
+    res = {k: np.concatenate(v) if v else np.zeros(0) for k, v in out.items()}
+    res["sec_e"] = np.concatenate(sec_e) if sec_e else np.zeros(0)
+    return res

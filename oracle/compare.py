@@ -1,17 +1,25 @@
 """Per-trajectory comparison of an endpoint set against the oracle's.
 
 TEST INFRASTRUCTURE ONLY.  Both inputs are numpy structured arrays with the
-128-byte endpoint layout (fields x0..e1, eid, parent, aval, status and the
-per-electron counters); nothing here imports the HIP package.
+136-byte endpoint layout (fields x0..e1, eid, parent, aval, status, the
+per-electron counters and the decision trace); nothing here imports the HIP
+package.
 
 Electrons are joined on their id (primaries 2^63 | index, secondaries a
 63-bit id drawn from the parent's random stream), which is unique within a
-run with overwhelming probability.  A matched electron is a *flip* when its
-decision trace differs from the oracle's -- any counter or the status
-differs -- or when an end coordinate differs by more than the tolerance
-(|d| <= rtol * max(|ref|, floor), floors 1e-4 cm, 1e-3 ns, 1e-3 eV).  The
-descendants of a flipped electron carry different ids and show up as
-unmatched, not as flips.
+run with overwhelming probability.  A matched electron is
+
+* a *decision flip* when its own decisions differ from the oracle's: its
+  decision trace (a hash over its real collisions, masked nulls and band
+  cuts, with their flight indices and channels), a counter, its status or
+  its parent differ.  Rounding can flip a decision whose margin is within
+  a few ulps; the descendants of a flipped electron carry different ids and
+  show up as unmatched, not as flips.
+* a *coordinate mismatch* when its decisions are the same but a start or
+  end coordinate differs by more than the tolerance (|d| <= rtol *
+  max(|ref|, floor), floors 1e-4 cm, 1e-3 ns, 1e-3 eV).  With the same
+  decisions the arithmetic between them is the same up to rounding, so this
+  must not happen at all.
 """
 from __future__ import annotations
 
@@ -19,7 +27,8 @@ import numpy as np
 
 FLOORS = {"x0": 1e-4, "y0": 1e-4, "z0": 1e-4, "t0": 1e-3, "e0": 1e-3,
           "x1": 1e-4, "y1": 1e-4, "z1": 1e-4, "t1": 1e-3, "e1": 1e-3}
-COUNTERS = ("aval", "status", "n_real", "n_ion", "n_null", "n_masked", "n_band", "n_overflow", "parent")
+DECISIONS = ("aval", "status", "n_real", "n_ion", "n_null", "n_masked", "n_band", "n_overflow",
+             "parent", "trace")
 
 
 def compare(got, ref, rtol=1e-9):
@@ -30,30 +39,42 @@ def compare(got, ref, rtol=1e-9):
     common, gi, ri = np.intersect1d(g_eid, r_eid, assume_unique=True, return_indices=True)
     G = got[gi]
     R = ref[ri]
-    bad = np.zeros(common.size, dtype=bool)
+    flip = np.zeros(common.size, dtype=bool)
+    for f in DECISIONS:
+        flip |= G[f] != R[f]
+    coord_bad = np.zeros(common.size, dtype=bool)
     max_rel = {}
     for f, floor in FLOORS.items():
         d = np.abs(G[f] - R[f])
         scale = np.maximum(np.abs(R[f]), floor)
         rel = d / scale
-        max_rel[f] = float(rel.max()) if rel.size else 0.0
-        bad |= ~(rel <= rtol)
-    for f in COUNTERS:
-        bad |= G[f] != R[f]
+        same = rel[~flip]
+        max_rel[f] = float(same.max()) if same.size else 0.0
+        coord_bad |= ~(rel <= rtol)
+    mismatch = coord_bad & ~flip
     n_match = int(common.size)
     return {
         "n_got": int(got.size), "n_ref": int(ref.size), "matched": n_match,
         "unmatched_got": int(got.size - n_match), "unmatched_ref": int(ref.size - n_match),
-        "flips": int(bad.sum()), "flip_fraction": float(bad.sum() / max(n_match, 1)),
+        "flips": int(flip.sum()), "flip_fraction": float(flip.sum() / max(n_match, 1)),
+        "coord_mismatches": int(mismatch.sum()),
         "max_rel": max_rel,
-        "flipped_eids": common[bad][:20].tolist(),
+        "flipped_eids": common[flip][:20].tolist(),
+        "mismatched_eids": common[mismatch][:20].tolist(),
     }
 
 
-def assert_parity(got, ref, rtol=1e-9, max_flip_fraction=1e-3, max_unmatched_fraction=0.01):
+def assert_parity(got, ref, rtol=1e-9, max_flip_fraction=1e-3, max_unmatched_fraction=0.01,
+                  max_flips=None):
+    """Coordinate mismatches: none.  Decision flips: below
+    max_flip_fraction of the matched electrons (and at most max_flips when
+    given, e.g. 0 where a path is expected to reproduce every decision)."""
     rep = compare(got, ref, rtol)
     assert rep["n_ref"] > 0
+    assert rep["coord_mismatches"] == 0, rep
     assert rep["flip_fraction"] < max_flip_fraction, rep
+    if max_flips is not None:
+        assert rep["flips"] <= max_flips, rep
     unm = max(rep["unmatched_got"], rep["unmatched_ref"]) / rep["n_ref"]
     assert unm <= max_unmatched_fraction, rep
     if rep["flips"] == 0:

@@ -25,20 +25,23 @@ ENDPOINT_DTYPE = np.dtype([
     ("eid", "<u8"), ("parent", "<u8"),
     ("aval", "<u4"), ("status", "<u4"), ("n_real", "<u4"), ("n_ion", "<u4"),
     ("n_null", "<u4"), ("n_masked", "<u4"), ("n_band", "<u4"), ("n_overflow", "<u4"),
+    ("trace", "<u4"), ("_pad", "<u4"),
 ])
-assert ENDPOINT_DTYPE.itemsize == 128
+assert ENDPOINT_DTYPE.itemsize == 136
 
 K_MAX_DEFAULT = (1 << 30) - 1
 
 
-def build(force: bool = True) -> str:
-    """Compile liboracle.so with gcc (plain C, FP64, no contraction)."""
-    if force or not os.path.exists(LIB_PATH):
+def build(force: bool = True, path: str = LIB_PATH, defines=()) -> str:
+    """Compile liboracle.so with gcc (plain C, FP64, no contraction).
+    ``defines``: extra macros (the ORC_PLANT_* switches of the pin tests)."""
+    if force or not os.path.exists(path):
         cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11", "-Wall",
-               "-fPIC", "-shared", "-pthread", "-o", LIB_PATH + ".tmp", SRC, "-lm"]
+               "-fPIC", "-shared", "-pthread"] + ["-D" + d for d in defines] + [
+               "-o", path + ".tmp", SRC, "-lm"]
         subprocess.run(cmd, check=True)
-        os.replace(LIB_PATH + ".tmp", LIB_PATH)
-    return LIB_PATH
+        os.replace(path + ".tmp", path)
+    return path
 
 
 class _Channel(C.Structure):
@@ -60,6 +63,13 @@ class _Signal(C.Structure):
 
 
 _lib = None
+_variants = {}
+
+
+def _load(path):
+    L = C.CDLL(path)
+    _declare(L)
+    return L
 
 
 def lib():
@@ -67,60 +77,91 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH) or os.path.getmtime(SRC) > os.path.getmtime(LIB_PATH):
             build()
-        L = C.CDLL(LIB_PATH)
-        dp, vp, u32p = C.POINTER(C.c_double), C.c_void_p, C.POINTER(C.c_uint32)
-        L.orc_gas_create.argtypes = [C.c_double, C.c_int32, C.c_double, C.c_int32,
-                                     C.POINTER(_Channel), C.c_int32, C.POINTER(vp)]
-        L.orc_gas_destroy.argtypes = [vp]
-        L.orc_gas_set_penning.argtypes = [vp, C.c_int32, C.c_double, C.c_double]
-        L.orc_gas_gamma.argtypes = [vp]
-        L.orc_gas_gamma.restype = C.c_double
-        L.orc_gas_n_bands.argtypes = [vp]
-        L.orc_gas_band.argtypes = [vp, C.c_int32, dp, dp]
-        L.orc_gas_set_gamma.argtypes = [vp, C.c_double]
-        L.orc_gas_rates.argtypes = [vp, C.c_double, dp, dp]
-        L.orc_gas_cumulative.argtypes = [vp, dp]
-        L.orc_gas_band_of.argtypes = [vp, C.c_double]
-        L.orc_field_slab.argtypes = [C.c_double, C.c_double, C.c_uint32, dp, dp, C.POINTER(vp)]
-        fp = C.POINTER(C.c_float)
-        L.orc_field_polar.argtypes = [C.c_double, C.c_double, C.c_int32, C.c_int32, fp, fp, dp,
-                                      C.POINTER(vp)]
-        L.orc_field_destroy.argtypes = [vp]
-        L.orc_field_eval.argtypes = [vp, dp, C.c_uint32, dp]
-        L.orc_run.argtypes = [vp, vp, vp, C.POINTER(C.c_uint64), C.c_uint64, C.POINTER(_Opts),
-                              C.POINTER(vp), C.POINTER(C.c_int32)]
-        L.orc_run_signal.argtypes = [vp, vp, vp, C.POINTER(C.c_uint64), C.c_uint64,
-                                     C.POINTER(_Opts), C.POINTER(_Signal), C.POINTER(vp),
-                                     C.POINTER(C.c_int32)]
-        L.orc_weighting.argtypes = [vp, dp]
-        L.orc_weighting.restype = C.c_double
-        L.orc_result_count.argtypes = [vp]
-        L.orc_result_count.restype = C.c_uint64
-        L.orc_result_copy.argtypes = [vp, vp]
-        L.orc_result_destroy.argtypes = [vp]
-        L.orc_philox4x32_10.argtypes = [u32p, u32p, u32p]
-        L.orc_u53.argtypes = [C.c_uint32, C.c_uint32]
-        L.orc_u53.restype = C.c_double
-        L.orc_u24.argtypes = [C.c_uint32]
-        L.orc_u24.restype = C.c_float
-        L.orc_cos_screened_rutherford.argtypes = [C.c_double, C.c_double, C.c_double]
-        L.orc_cos_screened_rutherford.restype = C.c_double
-        L.orc_split_energy.argtypes = [C.c_int32, C.c_double, C.c_double, C.c_double]
-        L.orc_split_energy.restype = C.c_double
-        L.orc_rotate.argtypes = [dp, C.c_double, C.c_double, dp]
-        L.orc_elastic.argtypes = [C.c_double, C.c_double, C.c_double, dp, dp]
-        L.orc_slab_exit.argtypes = [C.c_double] * 6 + [dp]
-        L.orc_band_root.argtypes = [dp, dp, C.c_double]
-        L.orc_band_root.restype = C.c_double
-        L.orc_propagate.argtypes = [dp, dp, dp, dp, C.c_double, dp, dp]
-        L.orc_helical_bound.argtypes = [dp, dp, dp, dp]
-        L.orc_helical_bound_root.argtypes = [dp, C.c_double]
-        L.orc_helical_bound_root.restype = C.c_double
-        L.orc_majorant_violations.restype = C.c_uint64
-        L.orc_k_a.restype = C.c_double
-        L.orc_k_b.restype = C.c_double
-        _lib = L
+        _lib = _load(LIB_PATH)
     return _lib
+
+
+class planted:
+    """Context in which the oracle is a build with one planted mistake
+    (``with planted("ORC_PLANT_PHI_SWAP"): ...``): the pin tests use it to
+    show that their pin fails on that mistake.  Objects made inside the
+    context belong to that build."""
+
+    def __init__(self, macro):
+        self.macro = macro
+
+    def __enter__(self):
+        global _lib
+        if self.macro not in _variants:
+            d = os.path.join(HERE, "_variants")
+            os.makedirs(d, exist_ok=True)
+            path = os.path.join(d, f"liboracle_{self.macro.lower()}.so")
+            build(True, path, (self.macro,))
+            _variants[self.macro] = _load(path)
+        lib()
+        self._saved = _lib
+        _lib = _variants[self.macro]
+        return self
+
+    def __exit__(self, *exc):
+        global _lib
+        _lib = self._saved
+        return False
+
+
+def _declare(L):
+    """Argument and result types of the C entry points."""
+    dp, vp, u32p = C.POINTER(C.c_double), C.c_void_p, C.POINTER(C.c_uint32)
+    L.orc_gas_create.argtypes = [C.c_double, C.c_int32, C.c_double, C.c_int32,
+                                 C.POINTER(_Channel), C.c_int32, C.POINTER(vp)]
+    L.orc_gas_destroy.argtypes = [vp]
+    L.orc_gas_set_penning.argtypes = [vp, C.c_int32, C.c_double, C.c_double]
+    L.orc_gas_gamma.argtypes = [vp]
+    L.orc_gas_gamma.restype = C.c_double
+    L.orc_gas_n_bands.argtypes = [vp]
+    L.orc_gas_band.argtypes = [vp, C.c_int32, dp, dp]
+    L.orc_gas_set_gamma.argtypes = [vp, C.c_double]
+    L.orc_gas_rates.argtypes = [vp, C.c_double, dp, dp]
+    L.orc_gas_cumulative.argtypes = [vp, dp]
+    L.orc_gas_band_of.argtypes = [vp, C.c_double]
+    L.orc_field_slab.argtypes = [C.c_double, C.c_double, C.c_uint32, dp, dp, C.POINTER(vp)]
+    fp = C.POINTER(C.c_float)
+    L.orc_field_polar.argtypes = [C.c_double, C.c_double, C.c_int32, C.c_int32, fp, fp, dp,
+                                  C.POINTER(vp)]
+    L.orc_field_destroy.argtypes = [vp]
+    L.orc_field_eval.argtypes = [vp, dp, C.c_uint32, dp]
+    L.orc_run.argtypes = [vp, vp, vp, C.POINTER(C.c_uint64), C.c_uint64, C.POINTER(_Opts),
+                          C.POINTER(vp), C.POINTER(C.c_int32)]
+    L.orc_run_signal.argtypes = [vp, vp, vp, C.POINTER(C.c_uint64), C.c_uint64,
+                                 C.POINTER(_Opts), C.POINTER(_Signal), C.POINTER(vp),
+                                 C.POINTER(C.c_int32)]
+    L.orc_weighting.argtypes = [vp, dp]
+    L.orc_weighting.restype = C.c_double
+    L.orc_result_count.argtypes = [vp]
+    L.orc_result_count.restype = C.c_uint64
+    L.orc_result_copy.argtypes = [vp, vp]
+    L.orc_result_destroy.argtypes = [vp]
+    L.orc_philox4x32_10.argtypes = [u32p, u32p, u32p]
+    L.orc_u53.argtypes = [C.c_uint32, C.c_uint32]
+    L.orc_u53.restype = C.c_double
+    L.orc_u24.argtypes = [C.c_uint32]
+    L.orc_u24.restype = C.c_float
+    L.orc_cos_screened_rutherford.argtypes = [C.c_double, C.c_double, C.c_double]
+    L.orc_cos_screened_rutherford.restype = C.c_double
+    L.orc_split_energy.argtypes = [C.c_int32, C.c_double, C.c_double, C.c_double]
+    L.orc_split_energy.restype = C.c_double
+    L.orc_rotate.argtypes = [dp, C.c_double, C.c_double, dp]
+    L.orc_elastic.argtypes = [C.c_double, C.c_double, C.c_double, dp, dp]
+    L.orc_slab_exit.argtypes = [C.c_double] * 6 + [dp]
+    L.orc_band_root.argtypes = [dp, dp, C.c_double]
+    L.orc_band_root.restype = C.c_double
+    L.orc_propagate.argtypes = [dp, dp, dp, dp, C.c_double, dp, dp]
+    L.orc_helical_bound.argtypes = [dp, dp, dp, dp]
+    L.orc_helical_bound_root.argtypes = [dp, C.c_double]
+    L.orc_helical_bound_root.restype = C.c_double
+    L.orc_majorant_violations.restype = C.c_uint64
+    L.orc_k_a.restype = C.c_double
+    L.orc_k_b.restype = C.c_double
 
 
 def _dptr(a):
@@ -132,6 +173,7 @@ class Gas:
 
     def __init__(self, gas, band_bins=None):
         L = lib()
+        self._L = L
         self._keep = []
         chans = (_Channel * len(gas.channels))()
         for i, ch in enumerate(gas.channels):
@@ -160,45 +202,46 @@ class Gas:
 
     def __del__(self):
         if getattr(self, "h", None):
-            lib().orc_gas_destroy(self.h)
+            self._L.orc_gas_destroy(self.h)
             self.h = None
 
     @property
     def gamma(self):
-        return lib().orc_gas_gamma(self.h)
+        return self._L.orc_gas_gamma(self.h)
 
     @property
     def n_bands(self):
-        return lib().orc_gas_n_bands(self.h)
+        return self._L.orc_gas_n_bands(self.h)
 
     def band(self, b):
         g, e = C.c_double(), C.c_double()
-        if lib().orc_gas_band(self.h, b, C.byref(g), C.byref(e)):
+        if self._L.orc_gas_band(self.h, b, C.byref(g), C.byref(e)):
             raise IndexError(b)
         return g.value, e.value
 
     def band_of(self, e):
-        return lib().orc_gas_band_of(self.h, e)
+        return self._L.orc_gas_band_of(self.h, e)
 
     def set_gamma(self, gamma):
-        if lib().orc_gas_set_gamma(self.h, gamma):
+        if self._L.orc_gas_set_gamma(self.h, gamma):
             raise ValueError("gamma below the table maximum")
 
     def rates(self, e):
         nu = np.zeros(self.n_ch)
         tot = C.c_double()
-        over = lib().orc_gas_rates(self.h, float(e), _dptr(nu), C.byref(tot))
+        over = self._L.orc_gas_rates(self.h, float(e), _dptr(nu), C.byref(tot))
         return nu, tot.value, bool(over)
 
     def cumulative(self):
         out = np.zeros((self.n_bins + 1, self.n_ch))
-        lib().orc_gas_cumulative(self.h, _dptr(out))
+        self._L.orc_gas_cumulative(self.h, _dptr(out))
         return out
 
 
 class Field:
     def __init__(self, field):
         L = lib()
+        self._L = L
         h = C.c_void_p()
         B = np.ascontiguousarray(getattr(field, "B_T", np.zeros(3)), dtype=np.float64)
         self._keep = [B]
@@ -221,18 +264,18 @@ class Field:
 
     def __del__(self):
         if getattr(self, "h", None):
-            lib().orc_field_destroy(self.h)
+            self._L.orc_field_destroy(self.h)
             self.h = None
 
     def weighting(self, r):
         """Weighting potential of the readout electrode at r (orc_weighting)."""
         rr = np.ascontiguousarray(r, dtype=np.float64)
-        return lib().orc_weighting(self.h, _dptr(rr))
+        return self._L.orc_weighting(self.h, _dptr(rr))
 
     def eval(self, r, aval=0):
         r = np.ascontiguousarray(r, dtype=np.float64)
         E = np.zeros(3)
-        lib().orc_field_eval(self.h, _dptr(r), aval, _dptr(E))
+        self._L.orc_field_eval(self.h, _dptr(r), aval, _dptr(E))
         return E
 
 
@@ -249,6 +292,8 @@ def run(gas, field, primaries, seed, *, banded=False, fifo=False, t_max=math.inf
     L = lib()
     g = gas if isinstance(gas, Gas) else Gas(gas)
     f = field if isinstance(field, Field) else Field(field)
+    if g._L is not L or f._L is not L:
+        raise ValueError("gas or field built by another oracle build (planted context)")
     prim = np.ascontiguousarray(primaries)
     if prim.dtype.itemsize != 72:
         raise ValueError("primary records must be 72 bytes")

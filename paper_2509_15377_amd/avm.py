@@ -32,7 +32,9 @@ ENDPOINT_DTYPE = np.dtype([
     ("eid", "<u8"), ("parent", "<u8"),
     ("aval", "<u4"), ("status", "<u4"), ("n_real", "<u4"), ("n_ion", "<u4"),
     ("n_null", "<u4"), ("n_masked", "<u4"), ("n_band", "<u4"), ("n_overflow", "<u4"),
+    ("trace", "<u4"), ("_pad", "<u4"),
 ])
+assert ENDPOINT_DTYPE.itemsize == 136
 
 
 class AvmError(RuntimeError):
@@ -81,7 +83,7 @@ TUNE_BANDS = 1
 class _EndpointArrays(C.Structure):
     _fields_ = [(n, C.c_void_p) for n in ("x0", "y0", "z0", "t0", "e0", "x1", "y1", "z1", "t1", "e1",
                                           "eid", "parent", "avalanche", "status", "n_real", "n_ion",
-                                          "n_null", "n_masked", "n_band", "n_overflow")]
+                                          "n_null", "n_masked", "n_band", "n_overflow", "trace")]
 
 
 # C entry points: name -> (argtypes, restype)

@@ -603,7 +603,7 @@ static size_t layout_store(Store& S, char* base, uint64_t cap) {
   take(&S.vx1, 8); take(&S.vy1, 8); take(&S.vz1, 8);
   take(&S.k1, 4); take(&S.band1, 4);
   take(&S.status, 4); take(&S.n_real, 4); take(&S.n_ion, 4); take(&S.n_null, 4);
-  take(&S.n_masked, 4); take(&S.n_band, 4); take(&S.n_over, 4);
+  take(&S.n_masked, 4); take(&S.n_band, 4); take(&S.n_over, 4); take(&S.trace, 4);
   S.capacity = cap;
   return off;
 }
@@ -966,6 +966,7 @@ avm_status avm_run_endpoints(const avm_run* r, uint64_t first, uint64_t n, avm_e
   AVM_GET(getu, aval, avalanche); AVM_GET(getu, status, status); AVM_GET(getu, n_real, n_real);
   AVM_GET(getu, n_ion, n_ion); AVM_GET(getu, n_null, n_null); AVM_GET(getu, n_masked, n_masked);
   AVM_GET(getu, n_band, n_band); AVM_GET(getu, n_over, n_overflow);
+  AVM_GET(getu, trace, trace);
 #undef AVM_GET
   return AVM_OK;
 }
@@ -977,7 +978,7 @@ avm_status avm_run_endpoint_arrays(const avm_run* r, avm_endpoint_arrays* out) {
   out->x1 = S.x1; out->y1 = S.y1; out->z1 = S.z1; out->t1 = S.t1; out->e1 = S.e1;
   out->eid = S.eid; out->parent = S.parent; out->avalanche = S.aval; out->status = S.status;
   out->n_real = S.n_real; out->n_ion = S.n_ion; out->n_null = S.n_null; out->n_masked = S.n_masked;
-  out->n_band = S.n_band; out->n_overflow = S.n_over;
+  out->n_band = S.n_band; out->n_overflow = S.n_over; out->trace = S.trace;
   return AVM_OK;
 }
 

@@ -2,9 +2,10 @@
 // for gfx950 (CDNA4, wave64).
 //
 // One call of `flight_step` is one pass of the AvalancheMicroscopic loop of
-// the paper's Fig. 2 ("position valid? -> find E and add a random time step
-// -> collision? -> ionisation or attachment?") for one electron held in
-// registers.  The free flight is a null-collision flight (Skullerud, cited in
+// the paper's Fig. 2 for one electron held in registers: check that it is
+// still inside the volume, take the local field and a random flight time,
+// decide whether a real collision ends the flight, and, for a real one,
+// which channel (an ionisation or an attachment changes the electron count).  The free flight is a null-collision flight (Skullerud, cited in
 // Sec. 1): exponential with the majorant rate, real with probability
 // nu(e)/majorant.  Both the plain (generation-synchronous) and the batched
 // (persistent) kernels call this same function, so for a given electron they
@@ -626,7 +627,10 @@ struct Elec {
   uint64_t eid;
   uint32_t aval, k;
   int32_t band;
-  uint32_t n_real, n_ion, n_null, n_masked, n_band, n_over;
+  // counters (null collisions are not counted here: every flight that goes
+  // on advances k, so k = n_null + n_masked + n_band + n_real - [attached])
+  uint32_t n_real, n_ion, n_masked, n_band, n_over;
+  uint32_t trace;  // decision trace (trace_step)
   R Ex, Ey, Ez;  // slab: the avalanche's field, loaded once per electron
   // induced signal: weighting potential where the current bin piece began,
   // time and index of the next bin edge
@@ -643,6 +647,17 @@ struct Child {
 };
 
 enum : int32_t { STEP_CONTINUE = 0, STEP_IONISED = 1, STEP_DONE = 2 };
+
+// Decision trace of an electron: a running 32-bit hash over its real
+// collisions, masked nulls and band cuts in flight order, so that two runs
+// can be told apart by the decisions an electron made (null collisions
+// enter through n_null).  Each event at flight index k maps h to
+// rotl(h, 5) ^ (k 2^18 + code), code = c for a real collision in channel
+// c, 2^16 + c for a masked null at channel c, 2^17 for a band cut.
+enum : uint32_t { TRACE_MASKED = 1u << 16, TRACE_BAND = 1u << 17 };
+AVM_FN uint32_t trace_step(uint32_t h, uint32_t k, uint32_t code) {
+  return ((h << 5) | (h >> 27)) ^ ((k << 18) + code);
+}
 
 // Precision-selected members of the gas and run parameters.
 template <class R> struct Sel;
@@ -978,8 +993,8 @@ AVM_FN void scatter_to(Elec<R>& e, const RunParams& P, R cos_t, R uB, R e_new) {
 }
 
 // Collision decision at energy en with selection value r_sel: -1 null,
-// -2 masked null (the chosen channel's window excludes en), otherwise the
-// channel: the smallest c with r_sel < interpolated cumulative rate c
+// -2 - c masked null (the chosen channel c's window excludes en), otherwise
+// the channel: the smallest c with r_sel < interpolated cumulative rate c
 // (channel 0 first -- the elastic channel dominates -- then a binary search
 // over the rest; interpolated cumulative rates are non-decreasing in c).
 // `margin` returns the smallest relative distance of r_sel to a rate it was
@@ -1074,7 +1089,7 @@ AVM_FN int decide(const GasDev& G, const TV& T, R en, R r_sel, R& margin, bool& 
     const double d = (dl < dh ? dl : dh) / (ed > 1e-30 ? ed : 1e-30);
     margin = (R)d < margin ? (R)d : margin;
   }
-  if (ed < e_lo || ed >= e_hi) return -2;
+  if (ed < e_lo || ed >= e_hi) return -2 - c;
   return c;
 }
 
@@ -1089,7 +1104,7 @@ AVM_FN int32_t flight_step(Elec<R>& e, const GasDev& G, const TV& T, const Field
                            const SignalDev* Q = nullptr) {
   using Mr = M<R>;
   constexpr bool kMixed = sizeof(R) == 4;
-  // position valid, flights and time left?
+  // still inside the volume, with flights and time left?
   uint32_t st0 = region_status<R, kField>(F, e);
   st0 = st0 ? st0 : (e.k >= P.k_max ? (uint32_t)ST_ABANDONED : (e.t >= P.t_max ? (uint32_t)ST_TIME : 0u));
   if (st0) {
@@ -1225,6 +1240,7 @@ AVM_FN int32_t flight_step(Elec<R>& e, const GasDev& G, const TV& T, const Field
       // advanced explicitly, never re-derived from the rounded energy
       e.band += 1;
       e.n_band += 1;
+      e.trace = trace_step(e.trace, e.k, TRACE_BAND);
     } else {
       // collision?
       const R en = dot3<R>(e.vx, e.vy, e.vz, e.vx, e.vy, e.vz) * Sel<R>::inv_2ka(P);
@@ -1244,12 +1260,13 @@ AVM_FN int32_t flight_step(Elec<R>& e, const GasDev& G, const TV& T, const Field
         if (over) e.n_over += 1;
         R e_band = en;  // energy whose band the next flight starts in
         if (c < 0) {
-          if (c == -1)
-            e.n_null += 1;
-          else
+          if (c != -1) {
             e.n_masked += 1;
+            e.trace = trace_step(e.trace, e.k, TRACE_MASKED + (uint32_t)(-2 - c));
+          }
         } else {
           e.n_real += 1;
+          e.trace = trace_step(e.trace, e.k, (uint32_t)c);
           const ChanP<R> ch = chan(G, T, c);
           const int32_t kind = ch.kind;
           if (kind == CH_ATTACHMENT) {

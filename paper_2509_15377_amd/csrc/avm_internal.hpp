@@ -32,6 +32,7 @@ struct Store {
   AVM_GLB double *x1, *y1, *z1, *t1, *e1, *vx1, *vy1, *vz1;
   AVM_GLB uint32_t *k1, *band1;
   AVM_GLB uint32_t *status, *n_real, *n_ion, *n_null, *n_masked, *n_band, *n_over;
+  AVM_GLB uint32_t* trace;  // decision trace (plain mode: running, between iterations)
   uint64_t capacity;
 };
 

@@ -180,7 +180,7 @@ __global__ void k_load_primaries(const PrimaryRec* __restrict__ prim, uint64_t n
     S.vx1[i] = sp * dx; S.vy1[i] = sp * dy; S.vz1[i] = sp * dz;
     S.k1[i] = 0; S.band1[i] = 0;
     S.n_real[i] = 0; S.n_ion[i] = 0; S.n_null[i] = 0; S.n_masked[i] = 0;
-    S.n_band[i] = 0; S.n_over[i] = 0; S.status[i] = 0;
+    S.n_band[i] = 0; S.n_over[i] = 0; S.status[i] = 0; S.trace[i] = 0;
     active[i] = (uint32_t)i;
   }
   S.qslot[i] = (uint32_t)i;
@@ -201,8 +201,12 @@ AVM_FN void write_end(const Store& S, uint32_t s, const Elec<R>& e, const RunPar
   S.x1[s] = e.x; S.y1[s] = e.y; S.z1[s] = e.z; S.t1[s] = e.t;
   S.e1[s] = (double)energy<R>(P, e.vx, e.vy, e.vz);
   S.status[s] = status;
-  S.n_real[s] = e.n_real; S.n_ion[s] = e.n_ion; S.n_null[s] = e.n_null;
+  // every flight that went on advanced k: nulls are what the other
+  // outcomes leave (an attachment ends the electron without advancing k)
+  const uint32_t n_null = e.k - e.n_masked - e.n_band - e.n_real + (status == ST_ATTACHED ? 1u : 0u);
+  S.n_real[s] = e.n_real; S.n_ion[s] = e.n_ion; S.n_null[s] = n_null;
   S.n_masked[s] = e.n_masked; S.n_band[s] = e.n_band; S.n_over[s] = e.n_over;
+  S.trace[s] = e.trace;
 }
 
 template <class R>
@@ -221,7 +225,8 @@ template <class R, bool kBanded, int kField, class TV>
 AVM_FN void load_elec_tail(const GasDev& G, const TV& T, const FieldDev& F,
                            const RunParams& P, Elec<R>& e) {
   e.k = 0;
-  e.n_real = 0; e.n_ion = 0; e.n_null = 0; e.n_masked = 0; e.n_band = 0; e.n_over = 0;
+  e.n_real = 0; e.n_ion = 0; e.n_masked = 0; e.n_band = 0; e.n_over = 0;
+  e.trace = 0;
   e.band = kBanded ? band_of<R>(G, T, energy<R>(P, e.vx, e.vy, e.vz)) : G.n_bands - 1;
   e.Ex = R(0); e.Ey = R(0); e.Ez = R(0);
   if (kField == FIELD_SLAB) slab_field<R>(F, e.aval, e);
@@ -257,8 +262,9 @@ __global__ void __launch_bounds__(kBlock) k_generation(GasDev G, FieldDev F, Run
     e.k = S.k1[slot];
     e.band = kBanded ? (e.k == 0 ? band_of<R>(G, T, energy<R>(P, e.vx, e.vy, e.vz)) : (int32_t)S.band1[slot])
                      : G.n_bands - 1;
-    e.n_real = S.n_real[slot]; e.n_ion = S.n_ion[slot]; e.n_null = S.n_null[slot];
+    e.n_real = S.n_real[slot]; e.n_ion = S.n_ion[slot];
     e.n_masked = S.n_masked[slot]; e.n_band = S.n_band[slot]; e.n_over = S.n_over[slot];
+    e.trace = S.trace[slot];
     e.Ex = R(0); e.Ey = R(0); e.Ez = R(0);
     if (kField == FIELD_SLAB) slab_field<R>(F, e.aval, e);
     uint32_t status = 0;
@@ -282,8 +288,9 @@ __global__ void __launch_bounds__(kBlock) k_generation(GasDev G, FieldDev F, Run
       S.x1[slot] = e.x; S.y1[slot] = e.y; S.z1[slot] = e.z; S.t1[slot] = e.t;
       S.vx1[slot] = (double)e.vx; S.vy1[slot] = (double)e.vy; S.vz1[slot] = (double)e.vz;
       S.k1[slot] = e.k; S.band1[slot] = (uint32_t)e.band;
-      S.n_real[slot] = e.n_real; S.n_ion[slot] = e.n_ion; S.n_null[slot] = e.n_null;
+      S.n_real[slot] = e.n_real; S.n_ion[slot] = e.n_ion;
       S.n_masked[slot] = e.n_masked; S.n_band[slot] = e.n_band; S.n_over[slot] = e.n_over;
+      S.trace[slot] = e.trace;
     }
   }
   // stack processing for this wave: slots for the secondaries, then the
@@ -296,7 +303,7 @@ __global__ void __launch_bounds__(kBlock) k_generation(GasDev G, FieldDev F, Run
     S.vx1[cs] = (double)child.vx; S.vy1[cs] = (double)child.vy; S.vz1[cs] = (double)child.vz;
     S.k1[cs] = 0; S.band1[cs] = 0;
     S.n_real[cs] = 0; S.n_ion[cs] = 0; S.n_null[cs] = 0; S.n_masked[cs] = 0;
-    S.n_band[cs] = 0; S.n_over[cs] = 0; S.status[cs] = 0;
+    S.n_band[cs] = 0; S.n_over[cs] = 0; S.status[cs] = 0; S.trace[cs] = 0;
   }
   const unsigned long long np = wave_alloc(&ctr->next, ionised);
   if (ionised) next[np] = slot;

@@ -223,6 +223,21 @@ def wire_polar_map(a_cm=25e-4, b_cm=0.5, volts=1500.0, n_r=512, n_phi=64,
     return PolarMapField(a_cm, b_cm, E_r, E_phi, np.asarray(B_T, dtype=np.float64))
 
 
+def wire_crossed_map(a_cm=25e-4, b_cm=0.5, volts=1500.0, E0_vcm=500.0, n_r=512, n_phi=64,
+                     B_T=(0.0, 0.0, 0.5)) -> PolarMapField:
+    """The wire field plus a uniform transverse field E0 along +x, sampled in
+    polar components at the same nodes: E_r = V/(r ln(b/a)) + E0 cos(phi),
+    E_phi = -E0 sin(phi) (float32).  It depends on phi and has E_phi != 0,
+    and its Cartesian closed form is V/(r^2 ln(b/a)) (x, y) + (E0, 0)."""
+    i = np.arange(n_r, dtype=np.float64)
+    r = a_cm * (b_cm / a_cm) ** (i / (n_r - 1))
+    phi = 2.0 * math.pi * np.arange(n_phi, dtype=np.float64) / n_phi
+    er = volts / (r * math.log(b_cm / a_cm))
+    E_r = (er[:, None] + E0_vcm * np.cos(phi)[None, :]).astype(np.float32)
+    E_phi = np.repeat((-E0_vcm * np.sin(phi))[None, :], n_r, axis=0).astype(np.float32)
+    return PolarMapField(a_cm, b_cm, E_r, E_phi, np.asarray(B_T, dtype=np.float64))
+
+
 # ---------------------------------------------------------------------------
 # The five workloads
 # ---------------------------------------------------------------------------
@@ -259,6 +274,18 @@ def wire(n_aval: int = 2048, band_bins: int = 0) -> Workload:
     p["y"] = 0.1 * np.sin(phi)
     return Workload("wire", argon_like_gas(band_bins=band_bins), wire_polar_map(), p, n_aval, 5,
                     "argon-like gas, wire counter 25 um / 5 mm / 1500 V polar map, 0.5 T axial B")
+
+
+def wire_crossed(n_aval: int = 256, band_bins: int = 0, rho_cm: float = 0.1) -> Workload:
+    """The wire chamber with an extra uniform transverse field of 500 V/cm
+    (a phi-dependent map with E_phi != 0), primaries at rest on a circle of
+    radius rho_cm at uniform azimuths (default_rng(7))."""
+    phi = np.random.default_rng(7).uniform(0.0, 2.0 * math.pi, n_aval)
+    p = primaries_at_rest(n_aval)
+    p["x"] = rho_cm * np.cos(phi)
+    p["y"] = rho_cm * np.sin(phi)
+    return Workload("wire_crossed", argon_like_gas(band_bins=band_bins), wire_crossed_map(), p,
+                    n_aval, 7, "argon-like gas, wire counter polar map plus 500 V/cm along x, 0.5 T axial B")
 
 
 def penning(n_aval: int = 500, band_bins: int = 0, prob: float = 0.05) -> Workload:

@@ -44,8 +44,8 @@ def test_library_exports_every_declared_symbol(A):
 
 
 def test_abi_version_and_sizes(A):
-    assert A.lib().avm_abi_version() == 1
-    assert A.ENDPOINT_DTYPE.itemsize == 128
+    assert A.lib().avm_abi_version() == 2
+    assert A.ENDPOINT_DTYPE.itemsize == 136
     assert W.PRIMARY_DTYPE.itemsize == 72
     assert C.sizeof(A._Counts) == 8 * 18 + 8
     assert C.sizeof(A._Opts) == 72
