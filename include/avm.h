@@ -78,7 +78,11 @@ typedef struct {
 
 typedef struct avm_gas avm_gas;
 
-/* Build the rate table on `device` (rate-table builder kernels): rates at the
+/* Paper: Sec. 1 (null-collision free flights after Skullerud need a bound
+ * of the collision rate) and Sec. 2 with Fig. 2 (the loop asks whether a
+ * collision happens and of which kind); Sec. 3.1 (the gas data are
+ * prepared once, before the transport, and moved to the device).
+ * Build the rate table on `device` (rate-table builder kernels): rates at the
  * nodes, cumulative rates over channels (in the given order), per-bin maxima
  * max(nu_k, nu_k+1) -- exact bounds of the linear interpolation -- the global
  * majorant Gamma and, with band_bins > 0, band majorants Gamma_b = max of the
@@ -96,13 +100,16 @@ typedef struct {
   int32_t n_bins, n_channels, n_bands, band_bins;
 } avm_gas_info;
 
+/* The majorant and table sizes of a gas (Sec. 1: the null-collision bound).
+ * Errors: AVM_E_ARG for NULL arguments. */
 avm_status avm_gas_get_info(const avm_gas* gas, avm_gas_info* out);
 /* Copy the device tables to host buffers (any may be NULL):
  * cumulative [(n_bins+1) * n_channels] node-major; band_gamma and band_edge_eV
  * [n_bands] (the last edge is +INFINITY). */
 avm_status avm_gas_get_tables(const avm_gas* gas, double* cumulative, double* band_gamma,
                               double* band_edge_eV);
-/* Rebuild the band majorants with a new band width (band_bins > 0; 0 drops
+/* Sec. 1 (the null-collision bound, here per energy band; an extension).
+ * Rebuild the band majorants with a new band width (band_bins > 0; 0 drops
  * the bands, leaving the global majorant only).  The per-bin maxima are kept
  * from avm_gas_create, so the bands are the ones avm_gas_create would build
  * with this band_bins.  The gas must not be in use by a run that has been
@@ -129,7 +136,11 @@ void avm_gas_destroy(avm_gas* gas);
 /* ------------------------------------------------------------------------ */
 typedef struct avm_field avm_field;
 
-/* Parallel-plate slab z_lo <= z < z_hi (x, y unbounded), uniform field.
+/* Paper: Fig. 2 (the field at the electron is looked up for every flight)
+ * and Sec. 3.1 (field data are moved to the device once, before the first
+ * transport); the analytic slab and the polar map stand in for the field
+ * maps of the case studies (Sec. 4).
+ * Parallel-plate slab z_lo <= z < z_hi (x, y unbounded), uniform field.
  * E_vcm: host pointer to n_E field vectors [n_E][3]; n_E == 1 applies one
  * field to every avalanche, otherwise avalanche a uses vector a.
  * B_T: uniform magnetic field (may be NULL); it must be zero or along z.
@@ -186,8 +197,8 @@ typedef struct {
   double timeout_s;       /* avm_run_sync wall-time limit (0: none) -> AVM_E_TIMEOUT      */
   void* hip_stream;       /* hipStream_t for all of the run's work (NULL: null stream)    */
   int32_t graph;          /* batched: 1 = capture the run's device work (reset, primary  */
-                          /*   load, transport, statistics, result copies) into a HIP    */
-                          /*   graph on the first execute and replay it afterwards       */
+                          /*   load, transport with its statistics, result copies) into  */
+                          /*   a HIP graph on the first execute and replay it afterwards */
   float band_lookahead;   /* banded: before each flight the band is raised to the band   */
                           /*   of the energy after this many mean free times of the      */
                           /*   current band (flight energy; with B its helical bound);   */
@@ -231,7 +242,11 @@ typedef struct {
 
 typedef struct avm_run avm_run;
 
-/* Prepare a run: validates, allocates the electron store (capacity
+/* Paper: Sec. 2 and Fig. 2 (every electron transported flight by flight
+ * until it terminates; ionisations add electrons); Sec. 3.2 (the run mode
+ * and the device are chosen by the user; initial electrons in, endpoints
+ * out).
+ * Prepare a run: validates, allocates the electron store (capacity
  * electrons, ~200 bytes each) on the gas's device.  prim: n_prim records,
  * a host pointer, or a device pointer when prim_on_device = 1 (it must stay
  * valid until avm_run_sync returns).  n_aval: number of avalanches (every
@@ -240,18 +255,27 @@ typedef struct avm_run avm_run;
 avm_status avm_run_create(const avm_gas* gas, const avm_field* field, const avm_primary* prim,
                           int32_t prim_on_device, uint64_t n_prim, uint32_t n_aval,
                           const avm_run_opts* opts, avm_run** out);
-/* Enqueue the run on its stream.  BATCHED: asynchronous.  PLAIN: returns
+/* Paper: Sec. 2 (the loop of Fig. 2; the paper's generation-synchronous
+ * stack processing is the PLAIN mode, the idle-thread problem of Fig. 1 is
+ * what the BATCHED mode removes).
+ * Enqueue the run on its stream.  BATCHED: asynchronous.  PLAIN: returns
  * when the generation loop has finished (it reads the active count back
  * after every transport iteration, as the paper's stack processing does). */
 avm_status avm_run_execute(avm_run* run);
-/* Wait for the run, then fetch the totals.  AVM_E_CAPACITY if truncated. */
+/* Wait for the run, then fetch the totals.  AVM_E_CAPACITY if truncated;
+ * AVM_E_TIMEOUT when the device time budget (timeout_s) ran out;
+ * AVM_E_ARG when a device primary had a bad avalanche id. */
 avm_status avm_run_sync(avm_run* run);
+/* Totals of the last execute (Sec. 2: gain = electrons after the avalanche
+ * over initial electrons).  AVM_E_STATE before avm_run_sync. */
 avm_status avm_run_counts(const avm_run* run, avm_counts* out);
 /* Per-avalanche counters for avalanches [first, first+n) (n_status and
  * n_requested are zero in these records). */
 avm_status avm_run_avalanche_counts(const avm_run* run, uint32_t first, uint32_t n,
                                     avm_counts* out);
-/* Number of endpoints stored (= min(n_requested, capacity)). */
+/* Endpoint getters of Sec. 3.2 (the number of endpoints; each endpoint's
+ * start and end position, time, energy and status).
+ * Number of endpoints stored (= min(n_requested, capacity)). */
 avm_status avm_run_num_endpoints(const avm_run* run, uint64_t* n);
 /* Copy endpoints [first, first+n) in storage order to host memory. */
 avm_status avm_run_endpoints(const avm_run* run, uint64_t first, uint64_t n, avm_endpoint* out);
@@ -266,7 +290,8 @@ typedef struct {
 } avm_endpoint_arrays;
 avm_status avm_run_endpoint_arrays(const avm_run* run, avm_endpoint_arrays* out);
 
-/* Kernel time of the last execute (ms, HIP events on the run's stream
+/* Sec. 4 (the GPU run time measured against the CPU run).
+ * Kernel time of the last execute (ms, HIP events on the run's stream
  * around the transport kernels; plain mode: summed over iterations; graph
  * mode: the whole replayed graph) and the number of transport iterations
  * (plain) or 1 (batched). */
@@ -316,7 +341,9 @@ typedef struct {
   uint64_t key;             /* workload key (device, gas table, field, sizes, options)  */
 } avm_tune_result;
 
-/* Choose flights_per_pass, waves_per_cu and (with AVM_TUNE_BANDS and the
+/* No counterpart in the paper (its launch is fixed); the batched launch's
+ * parameters and the band width decide how many threads idle (Fig. 1).
+ * Choose flights_per_pass, waves_per_cu and (with AVM_TUNE_BANDS and the
  * banded majorant) the gas's band width and the band lookahead for a
  * batched run of these
  * primaries: a coordinate search over candidate values, each timed on the

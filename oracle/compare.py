@@ -15,11 +15,22 @@ run with overwhelming probability.  A matched electron is
   its parent differ.  Rounding can flip a decision whose margin is within
   a few ulps; the descendants of a flipped electron carry different ids and
   show up as unmatched, not as flips.
-* a *coordinate mismatch* when its decisions are the same but a start or
-  end coordinate differs by more than the tolerance (|d| <= rtol *
+* a *coordinate mismatch* (drift) when its decisions are the same but a
+  start or end coordinate differs by more than the tolerance (|d| <= rtol *
   max(|ref|, floor), floors 1e-4 cm, 1e-3 ns, 1e-3 eV).  With the same
-  decisions the arithmetic between them is the same up to rounding, so this
-  must not happen at all.
+  decisions the arithmetic between them is the same up to rounding, but
+  ulp-level differences are not always damped along a trajectory: the
+  oracle against its own build with fused multiply-adds
+  (tests/test_oracle_rounding.py) shows, with the global majorant (tens of
+  thousands of flights per electron), about one electron in 1e5 drifting
+  past 1e-9 with every decision the same.  Some endpoints are also
+  ill-conditioned: a secondary born 1.5e-9 cm below the anode (argon-like
+  gas, 40 kV/cm) gains E (z_hi - z0) = 6e-5 eV on its way out, so a
+  difference of 3e-17 cm in its birth height (some twenty ulps, carried
+  from its parent's flights) is 1.2e-12 eV in its final energy, past
+  1e-9 of the 1e-3 eV floor.  Both are rounding-induced deviations with
+  identical decisions; they share the 0.1 % budget of the flips and are
+  bounded on their own by max_drift_fraction.
 """
 from __future__ import annotations
 
@@ -65,14 +76,16 @@ def compare(got, ref, rtol=1e-9):
 
 
 def assert_parity(got, ref, rtol=1e-9, max_flip_fraction=1e-3, max_unmatched_fraction=0.01,
-                  max_flips=None):
-    """Coordinate mismatches: none.  Decision flips: below
-    max_flip_fraction of the matched electrons (and at most max_flips when
-    given, e.g. 0 where a path is expected to reproduce every decision)."""
+                  max_flips=None, max_drift_fraction=1e-4):
+    """Decision flips and coordinate drifts (same decisions, a coordinate
+    beyond rtol) together: below max_flip_fraction of the matched
+    electrons; drifts alone at most max_drift_fraction; flips at most
+    max_flips when given (0 where a path reproduces every decision)."""
     rep = compare(got, ref, rtol)
     assert rep["n_ref"] > 0
-    assert rep["coord_mismatches"] == 0, rep
-    assert rep["flip_fraction"] < max_flip_fraction, rep
+    drift = rep["coord_mismatches"] / max(rep["matched"], 1)
+    assert drift <= max_drift_fraction, rep
+    assert rep["flip_fraction"] + drift < max_flip_fraction, rep
     if max_flips is not None:
         assert rep["flips"] <= max_flips, rep
     unm = max(rep["unmatched_got"], rep["unmatched_ref"]) / rep["n_ref"]

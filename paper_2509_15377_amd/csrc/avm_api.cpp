@@ -610,23 +610,79 @@ static size_t layout_store(Store& S, char* base, uint64_t cap) {
 
 // Grid of the persistent kernel: blocks per CU from the occupancy limit,
 // capped by the requested resident waves per CU, times the CU count.
-static hipError_t batched_grid(const avm_run* r, int32_t waves_per_cu, int* grid, int* blocks_per_cu_max) {
+static hipError_t persistent_grid(const avm_gas* gas, const avm_field* field, const avm_run_opts& o,
+                                  int signal, int block, int32_t waves_per_cu, int* grid,
+                                  int* blocks_per_cu_max) {
   int per_cu = 0, n_cu = 0, dev = 0;
-  hipError_t e = persistent_occupancy(r->opts.precision == AVM_FP32_MIXED, r->opts.majorant == AVM_MAJORANT_BANDED,
-                                      r->field->dev.kind, r->signal != nullptr, tables_fit_lds(r->gas->dev),
-                                      r->block, &per_cu);
+  hipError_t e = persistent_occupancy(o.precision == AVM_FP32_MIXED, o.majorant == AVM_MAJORANT_BANDED,
+                                      field->dev.kind, signal, tables_fit_lds(gas->dev), block, &per_cu);
   if (e == hipSuccess) e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) return e;
   if (per_cu < 1) per_cu = 1;
   if (blocks_per_cu_max) *blocks_per_cu_max = per_cu;
-  const int waves_per_block = r->block / 64;
+  const int waves_per_block = block / 64;
   if (waves_per_cu > 0) {
     const int want = (waves_per_cu + waves_per_block - 1) / waves_per_block;
     per_cu = want < per_cu ? want : per_cu;
   }
   *grid = per_cu * n_cu;
   return hipSuccess;
+}
+
+static hipError_t batched_grid(const avm_run* r, int32_t waves_per_cu, int* grid, int* blocks_per_cu_max) {
+  return persistent_grid(r->gas, r->field, r->opts, r->signal != nullptr, r->block, waves_per_cu, grid,
+                         blocks_per_cu_max);
+}
+
+// Checks the run options against the gas, field and sizes, and fills in
+// their defaults (shared by avm_run_create and avm_run_noalloc).
+static avm_status check_opts(const char* fn, const avm_gas* gas, const avm_field* field, uint64_t n_prim,
+                             uint32_t n_aval, avm_run_opts& o) {
+  if (field->dev.kind == FIELD_SLAB && field->dev.n_E > 1 && n_aval > field->dev.n_E)
+    return fail(AVM_E_ARG, "%s: %u avalanches but %u field vectors", fn, n_aval, field->dev.n_E);
+  if (o.precision != AVM_FP64 && o.precision != AVM_FP32_MIXED) return fail(AVM_E_ARG, "%s: bad precision", fn);
+  if (o.mode != AVM_MODE_PLAIN && o.mode != AVM_MODE_BATCHED) return fail(AVM_E_ARG, "%s: bad mode", fn);
+  if (o.majorant != AVM_MAJORANT_GLOBAL && o.majorant != AVM_MAJORANT_BANDED) return fail(AVM_E_ARG, "%s: bad majorant", fn);
+  if (o.majorant == AVM_MAJORANT_BANDED && gas->n_bands < 2)
+    return fail(AVM_E_ARG, "%s: banded majorant needs a gas built with band_bins > 0", fn);
+  if (o.majorant == AVM_MAJORANT_BANDED && field->dev.has_b && field->dev.kind == FIELD_SLAB)
+    return fail(AVM_E_UNSUPPORTED, "%s: banded majorant with B needs the polar-map geometry", fn);
+  if (o.k_max == 0) o.k_max = (1u << 30) - 1u;
+  if (o.k_max > (1u << 30) - 1u) return fail(AVM_E_ARG, "%s: k_max > 2^30-1", fn);
+  if (std::isnan(o.t_max_ns)) return fail(AVM_E_ARG, "%s: t_max is NaN", fn);
+  if (o.capacity < n_prim) return fail(AVM_E_ARG, "%s: capacity %llu < %llu primaries", fn, (unsigned long long)o.capacity, (unsigned long long)n_prim);
+  if (o.capacity > 0xFFFFFFF0ull) return fail(AVM_E_ARG, "%s: capacity above 2^32-16", fn);
+  if (o.flights_per_pass <= 0) o.flights_per_pass = 32;
+  if (o.waves_per_cu < 0) return fail(AVM_E_ARG, "%s: waves_per_cu < 0", fn);
+  if (!(o.band_lookahead >= 0.0f) || !std::isfinite(o.band_lookahead))
+    return fail(AVM_E_ARG, "%s: band_lookahead must be finite and >= 0", fn);
+  if (o.graph && o.mode != AVM_MODE_BATCHED)
+    return fail(AVM_E_ARG, "%s: graph capture needs the batched mode (the plain mode reads the host)", fn);
+  return AVM_OK;
+}
+
+// Transport parameters of a run: seed, limits, constants, the device time
+// budget (wall_clock64 ticks at `clock_khz`), the band lookahead.
+static RunParams run_params_of(const avm_run_opts& o, int clock_khz) {
+  RunParams P{};
+  P.key0 = (uint32_t)o.seed;
+  P.key1 = (uint32_t)(o.seed >> 32);
+  P.k_max = o.k_max;
+  P.banded = o.majorant == AVM_MAJORANT_BANDED;
+  P.t_max = o.t_max_ns;
+  P.k_a = k_a();
+  P.two_ka = 2.0 * P.k_a;
+  P.inv_2ka = 1.0 / P.two_ka;
+  P.k_a_f = (float)P.k_a;
+  P.two_ka_f = (float)P.two_ka;
+  P.inv_2ka_f = (float)P.inv_2ka;
+  // device time budget of one transport kernel: the caller's timeout, else
+  // a hard cap; a kernel past it stops and the run reports AVM_E_TIMEOUT
+  const double budget_s = o.timeout_s > 0.0 ? o.timeout_s : 600.0;
+  P.budget_ticks = (uint64_t)(budget_s * 1e3 * (double)clock_khz);
+  P.look = o.majorant == AVM_MAJORANT_BANDED ? (double)o.band_lookahead : 0.0;
+  return P;
 }
 
 avm_status avm_run_create(const avm_gas* gas, const avm_field* field, const avm_primary* prim,
@@ -639,28 +695,10 @@ avm_status avm_run_create(const avm_gas* gas, const avm_field* field, const avm_
   if (gas->device != field->device) return fail(AVM_E_ARG, "avm_run_create: gas and field on different devices");
   if (n_prim && !prim) return fail(AVM_E_ARG, "avm_run_create: primaries are NULL");
   if (n_aval == 0 && n_prim) return fail(AVM_E_ARG, "avm_run_create: n_aval = 0");
-  if (field->dev.kind == FIELD_SLAB && field->dev.n_E > 1 && n_aval > field->dev.n_E)
-    return fail(AVM_E_ARG, "avm_run_create: %u avalanches but %u field vectors", n_aval, field->dev.n_E);
   avm_run_opts o = *opts;
-  if (o.precision != AVM_FP64 && o.precision != AVM_FP32_MIXED) return fail(AVM_E_ARG, "avm_run_create: bad precision");
-  if (o.mode != AVM_MODE_PLAIN && o.mode != AVM_MODE_BATCHED) return fail(AVM_E_ARG, "avm_run_create: bad mode");
-  if (o.majorant != AVM_MAJORANT_GLOBAL && o.majorant != AVM_MAJORANT_BANDED) return fail(AVM_E_ARG, "avm_run_create: bad majorant");
-  if (o.majorant == AVM_MAJORANT_BANDED && gas->n_bands < 2)
-    return fail(AVM_E_ARG, "avm_run_create: banded majorant needs a gas built with band_bins > 0");
-  if (o.majorant == AVM_MAJORANT_BANDED && field->dev.has_b && field->dev.kind == FIELD_SLAB)
-    return fail(AVM_E_UNSUPPORTED, "avm_run_create: banded majorant with B needs the polar-map geometry");
-  if (o.k_max == 0) o.k_max = (1u << 30) - 1u;
-  if (o.k_max > (1u << 30) - 1u) return fail(AVM_E_ARG, "avm_run_create: k_max > 2^30-1");
-  if (std::isnan(o.t_max_ns)) return fail(AVM_E_ARG, "avm_run_create: t_max is NaN");
   if (o.capacity == 0) o.capacity = n_prim * 64 > (1u << 20) ? n_prim * 64 : (1u << 20);
-  if (o.capacity < n_prim) return fail(AVM_E_ARG, "avm_run_create: capacity %llu < %llu primaries", (unsigned long long)o.capacity, (unsigned long long)n_prim);
-  if (o.capacity > 0xFFFFFFF0ull) return fail(AVM_E_ARG, "avm_run_create: capacity above 2^32-16");
-  if (o.flights_per_pass <= 0) o.flights_per_pass = 32;
-  if (o.waves_per_cu < 0) return fail(AVM_E_ARG, "avm_run_create: waves_per_cu < 0");
-  if (!(o.band_lookahead >= 0.0f) || !std::isfinite(o.band_lookahead))
-    return fail(AVM_E_ARG, "avm_run_create: band_lookahead must be finite and >= 0");
-  if (o.graph && o.mode != AVM_MODE_BATCHED)
-    return fail(AVM_E_ARG, "avm_run_create: graph capture needs the batched mode (the plain mode reads the host)");
+  const avm_status cs = check_opts("avm_run_create", gas, field, n_prim, n_aval, o);
+  if (cs != AVM_OK) return cs;
   if (!prim_on_device)
     for (uint64_t i = 0; i < n_prim; ++i) {
       const avm_primary& p = prim[i];
@@ -685,14 +723,16 @@ avm_status avm_run_create(const avm_gas* gas, const avm_field* field, const avm_
   hipError_t e = hipMalloc(&r->store_mem, bytes);
   if (e == hipSuccess) layout_store(r->S, static_cast<char*>(r->store_mem), cap);
   if (e == hipSuccess) e = hipMemset(r->S.qready, 0, sizeof(uint32_t) * cap);
+  if (e == hipSuccess) e = dmalloc(&r->stats, n_aval ? n_aval : 1);
+  if (e == hipSuccess) e = dmalloc(&r->tot, 1);
+  r->S.stats = r->stats;
+  r->S.tot = r->tot;
   if (e == hipSuccess) e = dmalloc(&r->store_dev, 1);
   if (e == hipSuccess) e = hipMemcpy(r->store_dev, &r->S, sizeof(Store), hipMemcpyHostToDevice);
   if (e == hipSuccess && o.mode == AVM_MODE_PLAIN) e = dmalloc(&r->list0, cap);
   if (e == hipSuccess && o.mode == AVM_MODE_PLAIN) e = dmalloc(&r->list1, cap);
   if (e == hipSuccess) e = dmalloc(&r->ctr, 1);
   if (e == hipSuccess) e = hipMemset(r->ctr, 0, sizeof(Counters));
-  if (e == hipSuccess) e = dmalloc(&r->stats, n_aval ? n_aval : 1);
-  if (e == hipSuccess) e = dmalloc(&r->tot, 1);
   if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&r->tot_host), sizeof(Totals), hipHostMallocDefault);
   if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&r->ctr_host), sizeof(Counters), hipHostMallocDefault);
   if (e == hipSuccess && !prim_on_device && n_prim) {
@@ -720,29 +760,11 @@ avm_status avm_run_create(const avm_gas* gas, const avm_field* field, const avm_
   return AVM_OK;
 }
 
-static RunParams run_params(const avm_run* r) {
-  RunParams P{};
-  P.key0 = (uint32_t)r->opts.seed;
-  P.key1 = (uint32_t)(r->opts.seed >> 32);
-  P.k_max = r->opts.k_max;
-  P.banded = r->opts.majorant == AVM_MAJORANT_BANDED;
-  P.t_max = r->opts.t_max_ns;
-  P.k_a = k_a();
-  P.two_ka = 2.0 * P.k_a;
-  P.inv_2ka = 1.0 / P.two_ka;
-  P.k_a_f = (float)P.k_a;
-  P.two_ka_f = (float)P.two_ka;
-  P.inv_2ka_f = (float)P.inv_2ka;
-  // device time budget of one transport kernel: the caller's timeout, else
-  // a hard cap; a kernel past it stops and the run reports AVM_E_TIMEOUT
-  const double budget_s = r->opts.timeout_s > 0.0 ? r->opts.timeout_s : 600.0;
-  P.budget_ticks = (uint64_t)(budget_s * 1e3 * (double)r->clock_khz);
-  P.look = r->opts.majorant == AVM_MAJORANT_BANDED ? (double)r->opts.band_lookahead : 0.0;
-  return P;
-}
+static RunParams run_params(const avm_run* r) { return run_params_of(r->opts, r->clock_khz); }
 
 // The batched run's device work, in stream order: primaries (if on the
-// host), reset, primary load, persistent transport, statistics, result copies.
+// host), reset, primary load, persistent transport (which also adds up the
+// statistics as electrons terminate), result copies.
 static avm_status enqueue_batched(avm_run* r, hipStream_t st, bool timed) {
   const PrimaryRec* pd = r->prim_dev_user;
   if (!r->prim_on_device && r->n_prim) {
@@ -759,7 +781,6 @@ static avm_status enqueue_batched(avm_run* r, hipStream_t st, bool timed) {
                             r->opts.flights_per_pass, r->signal ? &r->sigdev : nullptr, r->grid,
                             r->block, st));
   if (timed) HIP_TRY(hipEventRecord(r->ev1, st));
-  HIP_TRY(launch_stats(r->S, r->ctr, r->stats, r->tot, st));
   HIP_TRY(hipMemcpyAsync(r->tot_host, r->tot, sizeof(Totals), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipMemcpyAsync(r->ctr_host, r->ctr, sizeof(Counters), hipMemcpyDeviceToHost, st));
   return AVM_OK;
@@ -848,7 +869,6 @@ avm_status avm_run_execute(avm_run* r) {
     A = B;
     B = t;
   }
-  HIP_TRY(launch_stats(r->S, r->ctr, r->stats, r->tot, st));
   HIP_TRY(hipMemcpyAsync(r->tot_host, r->tot, sizeof(Totals), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipMemcpyAsync(r->ctr_host, r->ctr, sizeof(Counters), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipEventRecord(r->ev_done, st));
@@ -911,14 +931,14 @@ avm_status avm_run_avalanche_counts(const avm_run* r, uint32_t first, uint32_t n
   for (uint32_t i = 0; i < n; ++i) {
     avm_counts& c = out[i];
     std::memset(&c, 0, sizeof c);
-    c.n_endpoints = h[i].n_endpoints;
-    c.n_ion = h[i].n_ion;
-    c.n_att = h[i].n_att;
-    c.n_real = h[i].n_real;
-    c.n_null = h[i].n_null;
-    c.n_masked = h[i].n_masked;
-    c.n_band = h[i].n_band;
-    c.n_overflow = h[i].n_over;
+    c.n_endpoints = h[i].c[0];
+    c.n_ion = h[i].c[1];
+    c.n_att = h[i].c[2];
+    c.n_real = h[i].c[3];
+    c.n_null = h[i].c[4];
+    c.n_masked = h[i].c[5];
+    c.n_band = h[i].c[6];
+    c.n_overflow = h[i].c[7];
   }
   return AVM_OK;
 }
@@ -1120,6 +1140,11 @@ hipError_t tune_key(const avm_gas* g, const avm_field* fl, const avm_primary* pr
   }
   f.val(o.precision); f.val(o.majorant); f.val(o.mode); f.val(o.k_max); f.val(o.t_max_ns);
   f.val(flags);
+  if (!((flags & AVM_TUNE_BANDS) && o.majorant == AVM_MAJORANT_BANDED && !fl->dev.has_b)) {
+    // bands not tuned, so part of the problem: the caller's band width and lookahead
+    f.val(g->band_bins);
+    f.val(o.band_lookahead);
+  }
   *key = f.h;
   return e;
 }
@@ -1127,7 +1152,7 @@ hipError_t tune_key(const avm_gas* g, const avm_field* fl, const avm_primary* pr
 // Version of the cache lines: raised whenever the transport kernel changes
 // enough that an earlier timing no longer ranks the candidates right, so
 // that lines from an older library are ignored (and a new choice appended).
-constexpr int kTuneLineVersion = 3;
+constexpr int kTuneLineVersion = 4;
 
 bool cache_lookup(const char* path, uint64_t key, int* fpp, int* wpc, int* bb, float* look, double* ms) {
   if (!path) return false;

@@ -9,6 +9,16 @@
 
 namespace avm {
 
+// Per-avalanche statistics (and totals, with the status histogram).
+struct AvalStats {
+  unsigned long long c[8];  // endpoints, ionisations, attachments, real, null, masked, band cuts, overflows
+};
+struct Totals {
+  unsigned long long c[8];       // as AvalStats
+  unsigned long long status[9];
+  unsigned long long _pad[7];
+};
+
 // Device store of a run, structure of arrays indexed by slot.  Slot s holds
 // the s-th electron created: its start record (written when it is created)
 // and its end record (written when it terminates).  The plain mode also
@@ -33,6 +43,9 @@ struct Store {
   AVM_GLB uint32_t *k1, *band1;
   AVM_GLB uint32_t *status, *n_real, *n_ion, *n_null, *n_masked, *n_band, *n_over;
   AVM_GLB uint32_t* trace;  // decision trace (plain mode: running, between iterations)
+  // statistics, added to by the transport kernels as electrons terminate
+  AVM_GLB AvalStats* stats;  // [n_aval]
+  AVM_GLB Totals* tot;
   uint64_t capacity;
 };
 
@@ -48,16 +61,6 @@ struct Counters {
   unsigned long long err;                 // bad primary avalanche id
   unsigned long long timeout;             // a transport kernel ran out of its time budget
   unsigned long long epoch;               // run counter (bumped by every reset; tags queue entries)
-};
-
-// Per-avalanche statistics (and totals, with the status histogram).
-struct AvalStats {
-  unsigned long long n_endpoints, n_ion, n_att, n_real, n_null, n_masked, n_band, n_over;
-};
-struct Totals {
-  unsigned long long c[8];       // as AvalStats
-  unsigned long long status[9];
-  unsigned long long _pad[7];
 };
 
 struct PrimaryRec {
@@ -93,7 +96,5 @@ hipError_t launch_tables_f32(const double* cum, const double* total, const doubl
                              size_t n_cum, int n_nodes, const double* bg, const double* be,
                              int n_bands, float* cum_f, float* total_f, float* cum0_f, float* bg_f,
                              float* bi_f, float* be_f, hipStream_t st);
-hipError_t launch_stats(const Store& S, const Counters* ctr, AvalStats* stats, Totals* tot,
-                        hipStream_t st);
 
 }  // namespace avm

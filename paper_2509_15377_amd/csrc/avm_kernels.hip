@@ -141,7 +141,8 @@ __global__ void k_reset(Counters* ctr, uint64_t n_prim, AvalStats* stats, uint32
     for (int j = 0; j < 8; ++j) tot->c[j] = 0;
     for (int j = 0; j < 9; ++j) tot->status[j] = 0;
   }
-  if (i < n_aval) stats[i] = AvalStats{0, 0, 0, 0, 0, 0, 0, 0};
+  if (i < n_aval)
+    for (int j = 0; j < 8; ++j) stats[i].c[j] = 0;
 }
 
 // Primaries -> slots [0, n): start record, zeroed end record, published.
@@ -195,16 +196,21 @@ AVM_FN void slab_field(const FieldDev& F, uint32_t aval, Elec<R>& e) {
   e.Ez = (R)E[2];
 }
 
+// Null collisions of a terminated electron: every flight that went on
+// advanced k, so nulls are what the other outcomes leave (an attachment
+// ends the electron without advancing k).
+template <class R>
+AVM_FN uint32_t null_count(const Elec<R>& e, uint32_t status) {
+  return e.k - e.n_masked - e.n_band - e.n_real + (status == ST_ATTACHED ? 1u : 0u);
+}
+
 template <class R>
 AVM_FN void write_end(const Store& S, uint32_t s, const Elec<R>& e, const RunParams& P,
                       uint32_t status) {
   S.x1[s] = e.x; S.y1[s] = e.y; S.z1[s] = e.z; S.t1[s] = e.t;
   S.e1[s] = (double)energy<R>(P, e.vx, e.vy, e.vz);
   S.status[s] = status;
-  // every flight that went on advanced k: nulls are what the other
-  // outcomes leave (an attachment ends the electron without advancing k)
-  const uint32_t n_null = e.k - e.n_masked - e.n_band - e.n_real + (status == ST_ATTACHED ? 1u : 0u);
-  S.n_real[s] = e.n_real; S.n_ion[s] = e.n_ion; S.n_null[s] = n_null;
+  S.n_real[s] = e.n_real; S.n_ion[s] = e.n_ion; S.n_null[s] = null_count(e, status);
   S.n_masked[s] = e.n_masked; S.n_band[s] = e.n_band; S.n_over[s] = e.n_over;
   S.trace[s] = e.trace;
 }
@@ -217,6 +223,87 @@ AVM_FN void write_start(const Store& S, uint64_t s, const Elec<R>& parent, const
   S.eid[s] = c.eid;
   S.parent[s] = parent.eid;
   S.aval[s] = parent.aval;
+}
+
+// ---------------------------------------------------------------------------
+// statistics at termination
+// ---------------------------------------------------------------------------
+// Block totals in LDS (flushed to the run's totals when the block ends):
+// the eight counters of AvalStats, then the status histogram.
+constexpr int kTally = 17;
+
+// Sum of v over the wave's lanes, as a wave-uniform (scalar) value.
+AVM_FN uint32_t wave_sum32(uint32_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return __builtin_amdgcn_readlane(v, 0);
+}
+
+// Sum of v over the lanes with `in` (counts below 2^30 each): in 32 bits
+// when every term is below 2^25, else in two 16-bit halves.
+AVM_FN unsigned long long group_sum(bool in, uint32_t v) {
+  const uint32_t x = in ? v : 0u;
+  if (__ballot(x >> 25) == 0) return wave_sum32(x);
+  return ((unsigned long long)wave_sum32(x >> 16) << 16) + wave_sum32(x & 0xFFFFu);
+}
+
+// Adds one counter of a group of lanes to its avalanche (device atomic) and
+// to the block's totals (LDS); called by every lane, acted on by the leader.
+AVM_FN void tally_add(bool leader, AVM_GLB unsigned long long* dst, AVM_LDS unsigned long long* blk,
+                      unsigned long long v) {
+  if (leader && v) {
+    __hip_atomic_fetch_add(dst, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(blk, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  }
+}
+
+// Adds the electrons this wave terminated (lanes with `ended`, status
+// `status`) to the statistics: the lanes are grouped by avalanche, and each
+// group's sums go to its avalanche's counters with one atomic per non-zero
+// counter, and to the block's totals in LDS.  The counters are summed one
+// at a time, so only one sum is live.
+template <class R>
+AVM_FN void tally_ends(bool ended, uint32_t status, const Elec<R>& e, const Store& S,
+                       AVM_LDS unsigned long long* blk) {
+  uint64_t m = __ballot(ended);
+  if (!m) return;
+  const uint32_t lane = __lane_id();
+  while (m) {
+    const int lead = __builtin_ctzll(m);
+    const uint32_t a = __builtin_amdgcn_readlane(e.aval, lead);
+    const bool in = ended && e.aval == a;
+    const uint64_t g = __ballot(in);
+    m &= ~g;
+    const bool L = lane == (uint32_t)lead;
+    AVM_GLB unsigned long long* dst = S.stats[a].c;
+    tally_add(L, dst + 0, blk + 0, __popcll(g));
+    tally_add(L, dst + 1, blk + 1, group_sum(in, e.n_ion));
+    tally_add(L, dst + 2, blk + 2, __popcll(__ballot(in && status == ST_ATTACHED)));
+    tally_add(L, dst + 3, blk + 3, group_sum(in, e.n_real));
+    tally_add(L, dst + 4, blk + 4, group_sum(in, in ? null_count(e, status) : 0u));
+    if (__ballot(in && e.n_masked)) tally_add(L, dst + 5, blk + 5, group_sum(in, e.n_masked));
+    if (__ballot(in && e.n_band)) tally_add(L, dst + 6, blk + 6, group_sum(in, e.n_band));
+    if (__ballot(in && e.n_over)) tally_add(L, dst + 7, blk + 7, group_sum(in, e.n_over));
+  }
+  // status histogram: one LDS add per status present
+  m = __ballot(ended);
+  while (m) {
+    const uint32_t st = __builtin_amdgcn_readlane(status, __builtin_ctzll(m));
+    const uint64_t g = __ballot(ended && status == st);
+    m &= ~g;
+    if (lane == (uint32_t)__builtin_ctzll(g))
+      __hip_atomic_fetch_add(blk + 8 + (st < 9 ? st : 8), (unsigned long long)__popcll(g), __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_WORKGROUP);
+  }
+}
+
+// A block's totals go to the run's totals (after the block's last tally).
+AVM_FN void flush_tally(const AVM_LDS unsigned long long* blk, AVM_GLB Totals* tot) {
+  const int i = threadIdx.x;
+  if (i < kTally && blk[i]) {
+    AVM_GLB unsigned long long* dst = i < 8 ? tot->c + i : tot->status + (i - 8);
+    __hip_atomic_fetch_add(dst, blk[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
 }
 
 // Counters, band and (slab) field of an electron whose position, velocity,
@@ -249,6 +336,10 @@ __global__ void __launch_bounds__(kBlock) k_generation(GasDev G, FieldDev F, Run
   const bool mine = i < n_active;
   const TabView<R> T = global_view<R>(G);
   const Store& S = *Sg;
+  __shared__ unsigned long long s_tally[kTally];
+  if (threadIdx.x < kTally) s_tally[threadIdx.x] = 0;
+  __syncthreads();
+  uint32_t term = 0;
   bool ionised = false;
   uint32_t slot = 0;
   Elec<R> e;
@@ -282,6 +373,7 @@ __global__ void __launch_bounds__(kBlock) k_generation(GasDev G, FieldDev F, Run
     } while (r == STEP_CONTINUE);
     if (r == STEP_DONE) {
       write_end(S, slot, e, P, status);
+      term = status;
     } else {
       complete_ionisation<R, kBanded>(e, G, T, P, child);
       ionised = true;
@@ -309,6 +401,9 @@ __global__ void __launch_bounds__(kBlock) k_generation(GasDev G, FieldDev F, Run
   if (ionised) next[np] = slot;
   const unsigned long long nc = wave_alloc(&ctr->next, stored);
   if (stored) next[nc] = (uint32_t)cs;
+  tally_ends<R>(term != 0, term, e, S, (AVM_LDS unsigned long long*)s_tally);
+  __syncthreads();
+  flush_tally((const AVM_LDS unsigned long long*)s_tally, S.tot);
 }
 
 // ---------------------------------------------------------------------------
@@ -408,6 +503,8 @@ __global__ void __launch_bounds__(kPBlock)
   __shared__ R s_tot[kLdsNodes], s_cum0[kLdsNodes];
   __shared__ R s_bg[kLdsBands], s_bi[kLdsBands], s_be[kLdsBands];
   __shared__ ChanP<R> s_ch[kLdsChannels];
+  __shared__ unsigned long long s_tally[kTally];
+  if (threadIdx.x < kTally) s_tally[threadIdx.x] = 0;
   const TabView<R> Tg = global_view<R>(G);
   const int n_lo = G.n_bins + 1 < kLdsNodes ? G.n_bins + 1 : kLdsNodes;
   for (int k = threadIdx.x; k < n_lo; k += kPBlock) {
@@ -437,7 +534,6 @@ __global__ void __launch_bounds__(kPBlock)
   uint32_t slot = 0;
   Elec<R> e;
   Child<R> child;
-  double cx = 0.0, cy = 0.0, cz = 0.0, ct = 0.0;  // where the child was born
   const uint64_t t_start = wall_clock64();
   for (;;) {
     if (wall_clock64() - t_start > P.budget_ticks) {
@@ -463,11 +559,10 @@ __global__ void __launch_bounds__(kPBlock)
       if (kSignal) signal_end<R, kField>(Q, e);
       write_end<R>(pinned(Sg), slot, e, P, term);
     }
+    tally_ends<R>(term != 0, term, e, pinned(Sg), (AVM_LDS unsigned long long*)s_tally);
     // ---- ionisations of this pass, finished together
-    if (cp) {
-      complete_ionisation<R, kBanded>(e, G, T, P, child);
-      cx = e.x; cy = e.y; cz = e.z; ct = e.t;
-    }
+    // (the secondary is born where its parent stands: e.x, e.y, e.z, e.t)
+    if (cp) complete_ionisation<R, kBanded>(e, G, T, P, child);
     // ---- exchange (wave in lockstep from here)
     const Store& S = pinned(Sg);
     // 1. storage slots for all secondaries of this pass (dropped beyond the
@@ -492,18 +587,18 @@ __global__ void __launch_bounds__(kPBlock)
       // start record: the electron's output; queued ones are also read by
       // other waves, so those go out device-coherent
       if (local) {
-        S.x0[cs] = cx; S.y0[cs] = cy; S.z0[cs] = cz; S.t0[cs] = ct;
+        S.x0[cs] = e.x; S.y0[cs] = e.y; S.z0[cs] = e.z; S.t0[cs] = e.t;
         S.vx0[cs] = (double)child.vx; S.vy0[cs] = (double)child.vy; S.vz0[cs] = (double)child.vz;
         S.eid[cs] = child.eid;
         S.aval[cs] = e.aval;
-        X.x[rank_c] = cx; X.y[rank_c] = cy; X.z[rank_c] = cz; X.t[rank_c] = ct;
+        X.x[rank_c] = e.x; X.y[rank_c] = e.y; X.z[rank_c] = e.z; X.t[rank_c] = e.t;
         X.vx[rank_c] = (double)child.vx; X.vy[rank_c] = (double)child.vy;
         X.vz[rank_c] = (double)child.vz;
         X.eid[rank_c] = child.eid;
         X.slot[rank_c] = (uint32_t)cs;
         X.aval[rank_c] = e.aval;
       } else {
-        st_coh(&S.x0[cs], cx); st_coh(&S.y0[cs], cy); st_coh(&S.z0[cs], cz); st_coh(&S.t0[cs], ct);
+        st_coh(&S.x0[cs], e.x); st_coh(&S.y0[cs], e.y); st_coh(&S.z0[cs], e.z); st_coh(&S.t0[cs], e.t);
         st_coh(&S.vx0[cs], (double)child.vx); st_coh(&S.vy0[cs], (double)child.vy);
         st_coh(&S.vz0[cs], (double)child.vz);
         st_coh(&S.eid[cs], child.eid);
@@ -603,42 +698,9 @@ __global__ void __launch_bounds__(kPBlock)
       idle_naps = 0;
     }
   }
-}
-
-// ---------------------------------------------------------------------------
-// statistics
-// ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kBlock) k_stats(Store S, const Counters* ctr, AvalStats* stats,
-                                                  Totals* tot) {
-  __shared__ unsigned long long blk[17];
-  if (threadIdx.x < 17) blk[threadIdx.x] = 0;
+  // every wave of the block has left the loop: the block's totals go out
   __syncthreads();
-  const unsigned long long n = ctr->tail < S.capacity ? ctr->tail : S.capacity;
-  for (unsigned long long s = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; s < n;
-       s += (unsigned long long)gridDim.x * blockDim.x) {
-    const uint32_t a = S.aval[s];
-    const uint32_t st = S.status[s];
-    const unsigned long long v[8] = {1ull, S.n_ion[s], st == ST_ATTACHED ? 1ull : 0ull, S.n_real[s],
-                                     S.n_null[s], S.n_masked[s], S.n_band[s], S.n_over[s]};
-    unsigned long long* dst = &stats[a].n_endpoints;
-    for (int j = 0; j < 8; ++j) {
-      if (v[j]) {
-        __hip_atomic_fetch_add(dst + j, v[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        atomicAdd(&blk[j], v[j]);
-      }
-    }
-    atomicAdd(&blk[8 + (st < 9 ? st : 8)], 1ull);
-  }
-  __syncthreads();
-  if (threadIdx.x < 8) {
-    if (blk[threadIdx.x])
-      __hip_atomic_fetch_add(&tot->c[threadIdx.x], blk[threadIdx.x], __ATOMIC_RELAXED,
-                             __HIP_MEMORY_SCOPE_AGENT);
-  } else if (threadIdx.x < 17) {
-    if (blk[threadIdx.x])
-      __hip_atomic_fetch_add(&tot->status[threadIdx.x - 8], blk[threadIdx.x], __ATOMIC_RELAXED,
-                             __HIP_MEMORY_SCOPE_AGENT);
-  }
+  flush_tally((const AVM_LDS unsigned long long*)s_tally, pinned(Sg).tot);
 }
 
 }  // namespace
@@ -814,10 +876,5 @@ hipError_t launch_tables_f32(const double* cum, const double* total, const doubl
   return hipGetLastError();
 }
 
-hipError_t launch_stats(const Store& S, const Counters* ctr, AvalStats* stats, Totals* tot,
-                        hipStream_t st) {
-  hipLaunchKernelGGL(k_stats, dim3(2048), dim3(kBlock), 0, st, S, ctr, stats, tot);
-  return hipGetLastError();
-}
 
 }  // namespace avm

@@ -68,7 +68,11 @@ def test_argon_global_subset(A, oracle_mod, mode):
     ref = oracle_mod.run(wl.gas, wl.field, prim, wl.seed)
     ep, tot, _ = A.run(wl, primaries=prim, n_aval=40, capacity=2_000_000,
                        mode=A.PLAIN if mode == "plain" else A.BATCHED)
-    rep = CMP.assert_parity(ep, ref)
+    # tens of thousands of null flights per electron: rounding drift past
+    # 1e-9 with identical decisions occurs here for the oracle against its
+    # own FMA build too (tests/test_oracle_rounding.py), so it shares the
+    # 0.1 % budget of rounding-induced deviations with the flips
+    rep = CMP.assert_parity(ep, ref, max_drift_fraction=1e-3)
     print("argon global", mode, rep)
     assert tot["n_null"] > 10 * tot["n_real"]
 
@@ -80,7 +84,7 @@ def test_argon_banded_batched(A, oracle_mod):
     ref = oracle_mod.run(g, wl.field, prim, wl.seed, banded=True)
     ep, tot, _ = A.run(wl, primaries=prim, n_aval=160, band_bins=100, majorant=A.BANDED,
                        capacity=4_000_000)
-    rep = CMP.assert_parity(ep, ref)
+    rep = CMP.assert_parity(ep, ref, max_flips=0)
     print("argon banded", rep)
     assert tot["n_band"] > 0 and tot["n_null"] < tot["n_real"]
 
@@ -106,7 +110,7 @@ def test_highgain_attachment_subset(A, oracle_mod):
     ref = oracle_mod.run(g, wl.field, prim, wl.seed, banded=True)
     ep, tot, _ = A.run(wl, primaries=prim, n_aval=2, band_bins=100, majorant=A.BANDED,
                        capacity=2_000_000)
-    rep = CMP.assert_parity(ep, ref)
+    rep = CMP.assert_parity(ep, ref, max_flips=0)
     print("highgain", rep)
     assert tot["n_att"] > 0
 
@@ -139,7 +143,7 @@ def test_full_argon_bench_configuration_sampled(A, oracle_mod):
     ref = oracle_mod.run(g, wl.field, wl.primaries[idx], wl.seed, banded=True, ids=idx,
                          band_lookahead=1.0)
     sub = ep[(ep["aval"] % 50) == 0]
-    rep = CMP.assert_parity(sub, ref)
+    rep = CMP.assert_parity(sub, ref, max_flips=0)
     print("argon full sampled", rep, "electrons", tot["n_endpoints"])
 
 
@@ -268,6 +272,6 @@ def test_tables_beyond_the_lds_copies(A, oracle_mod, case):
                          band_lookahead=1.0)
     ep, tot, _ = A.run(gas=g, field=A.Field(wl.field), primaries=prim, n_aval=24, seed=wl.seed,
                        majorant=A.BANDED, band_lookahead=1.0, capacity=4_000_000)
-    rep = CMP.assert_parity(ep, ref)
+    rep = CMP.assert_parity(ep, ref, max_flips=0)
     print("beyond LDS", case, rep)
     assert tot["n_ion"] > 0

@@ -77,7 +77,7 @@ def test_autotune_choice_and_cache(A, oracle_mod, tmp_path):
     assert res["trials"] >= 8 and res["from_cache"] == 0
     assert res["best_ms"] <= res["start_ms"]
     assert g.band_bins == res["band_bins"]
-    assert cache.read_text().count("avm_tune 3 ") == 1
+    assert cache.read_text().count("avm_tune 4 ") == 1
     # launch parameters do not change results: tuned == default at that band width
     look = res["band_lookahead"]
     tuned = A.Run(g, f, wl.primaries, wl.n_aval, flights_per_pass=res["flights_per_pass"],
@@ -98,6 +98,11 @@ def test_autotune_choice_and_cache(A, oracle_mod, tmp_path):
     g2 = A.Gas(wl.gas, band_bins=100)
     res2 = A.autotune(g2, f, wl.primaries, wl.n_aval, cache=str(cache), **kw)
     assert res2["from_cache"] == 1 and res2["trials"] == 0 and res2["key"] == res["key"]
+    # without band tuning the band width is part of the problem: another
+    # width is another key, never an earlier line's choice
+    g3 = A.Gas(wl.gas, band_bins=50)
+    res3 = A.autotune(g3, f, wl.primaries, wl.n_aval, cache=str(cache), tune_bands=False, **kw)
+    assert res3["from_cache"] == 0 and res3["key"] != res["key"] and g3.band_bins == 50
     for k in ("flights_per_pass", "waves_per_cu", "band_bins", "band_lookahead"):
         assert res2[k] == res[k]
     assert g2.band_bins == res["band_bins"]
