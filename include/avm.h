@@ -363,6 +363,61 @@ avm_status avm_autotune(avm_gas* gas, const avm_field* field, const avm_primary*
                         const avm_run_opts* base, uint32_t flags, const char* cache_path,
                         avm_tune_result* out);
 
+/* ------------------------------------------------------------------------ */
+/* Batched transport that allocates nothing                                   */
+/* ------------------------------------------------------------------------ */
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  The same
+ * transport as avm_run_execute in the batched mode (same kernels, same
+ * results for the same inputs and options), with the caller's arrays as
+ * the outputs.  Its working memory -- run counters, queue entries, the
+ * start velocities of queued electrons, the store descriptor and the
+ * totals -- is one static device array of the library per GPU, of
+ * 32 bytes x AVM_NOALLOC_MAX_ELECTRONS + 4 KiB (128 MiB), which each GPU the
+ * library runs on holds until the process ends.  Every call on a GPU shares
+ * that GPU's array, so calls that overlap on one GPU (on different streams,
+ * or from different threads) race and give wrong results: serialise them.
+ * Nothing is allocated or freed, on the host or the device, after the
+ * first call on a device (which looks up the array's device address).
+ *
+ * prim: device pointer, n_prim records (as avm_run_create with
+ *   prim_on_device = 1; a bad avalanche id sets AVM_NOALLOC_BAD_AVALANCHE).
+ * opts: mode must be AVM_MODE_BATCHED and graph 0; capacity is the length of
+ *   every per-electron output array (1 <= capacity <=
+ *   AVM_NOALLOC_MAX_ELECTRONS, and >= n_prim); hip_stream is where the work
+ *   is enqueued; timeout_s bounds the transport kernel on the device (the
+ *   flag AVM_NOALLOC_TIMEOUT), nothing waits on the host.
+ * out: device pointers, caller-owned.  The per-electron arrays are indexed
+ *   by storage slot as in avm_endpoint_arrays (slots [0, min(n_requested,
+ *   capacity)) are written); aval_counts [n_aval][8] receives the
+ *   per-avalanche counters (endpoints, ionisations, attachments, real,
+ *   null, masked, band cuts, overflows) and is cleared first; counts
+ *   receives one avm_counts record of totals, flags one word of
+ *   AVM_NOALLOC_* bits.
+ * Asynchronous: returns once the work is enqueued; results are valid after
+ * the stream has reached this point.  Errors (nothing enqueued): AVM_E_ARG
+ * for NULL arguments or arrays, a capacity outside the limits, options as
+ * avm_run_create, a mode other than batched, graph != 0; AVM_E_HIP for a
+ * failing launch. */
+#define AVM_NOALLOC_MAX_ELECTRONS 4194304u
+#define AVM_NOALLOC_TIMEOUT 1u        /* the transport kernel ran out of its time budget */
+#define AVM_NOALLOC_BAD_AVALANCHE 2u  /* a primary's avalanche id was >= n_aval          */
+#define AVM_NOALLOC_TRUNCATED 4u      /* electrons beyond capacity were dropped           */
+
+typedef struct {
+  double *x0, *y0, *z0, *t0, *e0, *x1, *y1, *z1, *t1, *e1;
+  uint64_t *eid, *parent;
+  uint32_t *avalanche, *status, *n_real, *n_ion, *n_null, *n_masked, *n_band, *n_overflow;
+  uint32_t* trace;
+  uint64_t* aval_counts; /* [n_aval][8]                       */
+  avm_counts* counts;    /* one record                         */
+  uint32_t* flags;       /* one word of AVM_NOALLOC_* bits     */
+} avm_noalloc_out;
+
+avm_status avm_run_noalloc(const avm_gas* gas, const avm_field* field, const avm_primary* prim,
+                           uint64_t n_prim, uint32_t n_aval, const avm_run_opts* opts,
+                           const avm_noalloc_out* out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -86,6 +86,20 @@ class _EndpointArrays(C.Structure):
                                           "n_null", "n_masked", "n_band", "n_overflow", "trace")]
 
 
+NOALLOC_MAX_ELECTRONS = 4194304
+NOALLOC_TIMEOUT, NOALLOC_BAD_AVALANCHE, NOALLOC_TRUNCATED = 1, 2, 4
+_NOALLOC_ARRAYS = (("x0", "f8"), ("y0", "f8"), ("z0", "f8"), ("t0", "f8"), ("e0", "f8"),
+                   ("x1", "f8"), ("y1", "f8"), ("z1", "f8"), ("t1", "f8"), ("e1", "f8"),
+                   ("eid", "u8"), ("parent", "u8"), ("avalanche", "u4"), ("status", "u4"),
+                   ("n_real", "u4"), ("n_ion", "u4"), ("n_null", "u4"), ("n_masked", "u4"),
+                   ("n_band", "u4"), ("n_overflow", "u4"), ("trace", "u4"))
+
+
+class _NoallocOut(C.Structure):
+    _fields_ = [(n, C.c_void_p) for n, _ in _NOALLOC_ARRAYS] + [
+        ("aval_counts", C.c_void_p), ("counts", C.c_void_p), ("flags", C.c_void_p)]
+
+
 # C entry points: name -> (argtypes, restype)
 _VP = C.c_void_p
 _DP = C.POINTER(C.c_double)
@@ -120,6 +134,8 @@ _SIGS = {
     "avm_run_signal": ([_VP, C.c_uint32, C.c_uint32, _DP], C.c_int),
     "avm_autotune": ([_VP, _VP, _VP, C.c_int32, C.c_uint64, C.c_uint32, C.POINTER(_Opts), C.c_uint32,
                       C.c_char_p, C.POINTER(_TuneResult)], C.c_int),
+    "avm_run_noalloc": ([_VP, _VP, _VP, C.c_uint64, C.c_uint32, C.POINTER(_Opts),
+                         C.POINTER(_NoallocOut)], C.c_int),
 }
 EXPORTED = tuple(_SIGS)
 
@@ -400,6 +416,56 @@ class Run:
             self.close()
         except Exception:  # interpreter shutdown: the library may be gone
             pass
+
+
+def noalloc_outputs(capacity: int, n_aval: int, device="cuda:0"):
+    """Output tensors for avm_run_noalloc (the caller's memory: allocated
+    here, by torch, before the call)."""
+    import torch
+    dt = {"f8": torch.float64, "u8": torch.int64, "u4": torch.int32}
+    out = {n: torch.zeros(capacity, dtype=dt[k], device=device) for n, k in _NOALLOC_ARRAYS}
+    out["aval_counts"] = torch.zeros((max(n_aval, 1), 8), dtype=torch.int64, device=device)
+    out["counts"] = torch.zeros(C.sizeof(_Counts), dtype=torch.uint8, device=device)
+    out["flags"] = torch.zeros(1, dtype=torch.int32, device=device)
+    return out
+
+
+def run_noalloc(gas: Gas, field: Field, primaries, n_aval: int, out: dict, *, seed: int,
+                precision=FP64, majorant=GLOBAL, t_max=math.inf, k_max=0, flights_per_pass=0,
+                waves_per_cu=0, timeout_s=0.0, stream=None, band_lookahead=0.0):
+    """avm_run_noalloc: the batched transport into the caller's output
+    tensors ``out`` (see noalloc_outputs; capacity = their length), with the
+    primaries a GPU tensor of 72-byte records.  Enqueued on ``stream``;
+    returns at once."""
+    ptr, on_dev, n_prim, keep = _primaries_arg(primaries)
+    if not on_dev:
+        raise ValueError("avm_run_noalloc takes device primaries")
+    cap = out["x0"].numel()
+    o = _make_opts(seed, precision, majorant, BATCHED, flights_per_pass, t_max, cap, k_max,
+                   waves_per_cu, timeout_s, stream, False, band_lookahead)
+    st = _NoallocOut(*[C.c_void_p(out[n].data_ptr()) for n, _ in _NOALLOC_ARRAYS],
+                     C.c_void_p(out["aval_counts"].data_ptr()), C.c_void_p(out["counts"].data_ptr()),
+                     C.c_void_p(out["flags"].data_ptr()))
+    _check(lib().avm_run_noalloc(gas.h, field.h, ptr, n_prim, int(n_aval), C.byref(o), C.byref(st)),
+           "avm_run_noalloc")
+    del keep
+
+
+def noalloc_results(out: dict, n_aval: int):
+    """(endpoints sorted by (avalanche, eid), totals dict, per-avalanche
+    counts dict, flags) from the output tensors of a finished run_noalloc."""
+    c = _Counts.from_buffer_copy(out["counts"].cpu().numpy().tobytes())
+    tot = _counts_dict(c)
+    n = min(tot["n_requested"], out["x0"].numel())
+    ep = np.zeros(n, dtype=ENDPOINT_DTYPE)
+    names = {"avalanche": "aval", "n_overflow": "n_overflow"}
+    for name, _ in _NOALLOC_ARRAYS:
+        ep[names.get(name, name)] = out[name][:n].cpu().numpy().view(ENDPOINT_DTYPE[names.get(name, name)])
+    ep = ep[np.lexsort((ep["eid"], ep["aval"]))]
+    ac = out["aval_counts"][:n_aval].cpu().numpy().view(np.uint64).astype(np.int64)
+    keys = ("n_endpoints", "n_ion", "n_att", "n_real", "n_null", "n_masked", "n_band", "n_overflow")
+    per = {k: ac[:, j] for j, k in enumerate(keys)}
+    return ep, tot, per, int(out["flags"].cpu().item())
 
 
 def run(workload=None, *, gas=None, field=None, primaries=None, n_aval=None, seed=None,

@@ -11,7 +11,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB_DIR = os.path.join(PKG, "_lib")
 LIB_PATH = os.path.join(LIB_DIR, "libavm.so")
-SOURCES = ["avm_kernels.hip", "avm_api.cpp"]
+SOURCES = ["avm_kernels.hip", "avm_api.cpp", "avm_noalloc.hip"]
 
 # -ffp-contract=off: no implicit a*b+c fusion, so a device function gives the
 # same bits in every kernel that inlines it.  Packed FP32 instructions are

@@ -1084,6 +1084,50 @@ void avm_run_destroy(avm_run* r) {
 }  // extern "C"
 
 // ---------------------------------------------------------------------------
+// no-allocation runs: validation and launch parameters (the entry point
+// itself is in avm_noalloc.hip, beside its scratch array)
+// ---------------------------------------------------------------------------
+avm_status avm::set_error(avm_status st, const char* msg) {
+  g_err = msg ? msg : "";
+  return st;
+}
+
+avm_status avm::noalloc_setup(const avm_gas* gas, const avm_field* field, uint64_t n_prim, uint32_t n_aval,
+                              const avm_run_opts* opts, uint64_t max_electrons, NoallocSetup* out) {
+  g_err.clear();
+  if (!gas || !field || !opts || !out) return fail(AVM_E_ARG, "avm_run_noalloc: NULL argument");
+  if (gas->device != field->device) return fail(AVM_E_ARG, "avm_run_noalloc: gas and field on different devices");
+  if (n_aval == 0 && n_prim) return fail(AVM_E_ARG, "avm_run_noalloc: n_aval = 0");
+  avm_run_opts o = *opts;
+  if (o.mode != AVM_MODE_BATCHED) return fail(AVM_E_ARG, "avm_run_noalloc: only the batched mode allocates nothing");
+  if (o.graph) return fail(AVM_E_ARG, "avm_run_noalloc: graph must be 0 (a caller may capture the call itself)");
+  if (o.capacity == 0) return fail(AVM_E_ARG, "avm_run_noalloc: capacity must be the length of the output arrays");
+  if (o.capacity > max_electrons)
+    return fail(AVM_E_ARG, "avm_run_noalloc: capacity %llu above the scratch limit %llu",
+                (unsigned long long)o.capacity, (unsigned long long)max_electrons);
+  const avm_status cs = check_opts("avm_run_noalloc", gas, field, n_prim, n_aval, o);
+  if (cs != AVM_OK) return cs;
+  DeviceGuard dg(gas->device);
+  if (dg.err != hipSuccess) return fail(AVM_E_HIP, "hipSetDevice: %s", hipGetErrorString(dg.err));
+  NoallocSetup& S = *out;
+  S.device = gas->device;
+  S.gas = gas->dev;
+  S.field = field->dev;
+  int khz = 0;
+  if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, gas->device) != hipSuccess || khz <= 0)
+    khz = 100000;
+  S.params = run_params_of(o, khz);
+  S.fp32 = o.precision == AVM_FP32_MIXED;
+  S.banded = o.majorant == AVM_MAJORANT_BANDED;
+  S.field_kind = field->dev.kind;
+  S.flights_per_pass = o.flights_per_pass;
+  S.block = persistent_block();
+  S.k_a = k_a();
+  HIP_TRY(persistent_grid(gas, field, o, 0, S.block, o.waves_per_cu, &S.grid, nullptr));
+  return AVM_OK;
+}
+
+// ---------------------------------------------------------------------------
 // autotuning
 // ---------------------------------------------------------------------------
 namespace {

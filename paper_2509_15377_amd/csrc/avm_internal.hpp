@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "avm.h"
 #include "avm_device.hpp"
 
 namespace avm {
@@ -67,6 +68,24 @@ struct PrimaryRec {
   double x, y, z, t, e, dx, dy, dz;
   uint32_t aval, _pad;
 };
+
+// Everything the no-allocation entry point (avm_noalloc.hip) launches with:
+// validated options turned into the kernels' parameter blocks.
+struct NoallocSetup {
+  int device;
+  GasDev gas;
+  FieldDev field;
+  RunParams params;
+  int fp32, banded, field_kind, flights_per_pass, grid, block;
+  double k_a;
+};
+
+// ---- host side (avm_api.cpp) ----
+// Validates a no-allocation run and fills `out` (message set on error).
+avm_status noalloc_setup(const avm_gas* gas, const avm_field* field, uint64_t n_prim, uint32_t n_aval,
+                         const avm_run_opts* opts, uint64_t max_electrons, NoallocSetup* out);
+// Sets the thread's error text (avm_last_error) and returns st.
+avm_status set_error(avm_status st, const char* msg);
 
 // ---- launchers (avm_kernels.hip) ----
 hipError_t launch_build_rates(const double* sigma, const int32_t* values_kind, int n_ch, int n_bins,
