@@ -26,7 +26,20 @@ if ROOT not in sys.path:
 OPS_PER_FLIGHT = 150
 OPS_PER_REAL = 220
 OPS_PER_ION = 280
+# the polar map and the magnetic field add, per flight: the map gather
+# (log of rho^2, azimuth, four-node bilinear weights and eight reads, the
+# rotation to Cartesian, ~95), the helical step (sin/cos of the gyration
+# phase and half of it, drift and gyration terms, ~105) and, with the band
+# majorant, the helical energy bound (three square roots, ~40)
+OPS_PER_FLIGHT_POLAR_B = 240
 PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
+
+
+def lane_ops(c, polar_b=False):
+    """Algorithmic lane operations of a run from its counts."""
+    flights = c["n_real"] + c["n_null"] + c["n_masked"] + c["n_band"]
+    per_flight = OPS_PER_FLIGHT + (OPS_PER_FLIGHT_POLAR_B if polar_b else 0)
+    return flights * per_flight + c["n_real"] * OPS_PER_REAL + c["n_ion"] * OPS_PER_ION
 
 # Oracle samples per workload (avalanche ids divisible by the modulus, which
 # replay exactly on their own): about 5-30 s on the host cores.  Electron
@@ -118,25 +131,74 @@ def side_legs(args, make, timed, paths, gas, field, wl, capacity, stream):
     sr.close()
 
 
-def crossover():
+def workload_leg(name, precision, steps, warmup, stream):
+    """One benchmark workload in the headline's launch configuration
+    (batched, banded majorant of 100-bin bands, lookahead 1, graph replay,
+    primaries in HBM): ms per step, rates and the transport kernel's own
+    roofline fraction."""
+    import numpy as np
+    import torch
+
+    from paper_2509_15377_amd import avm, workloads as W
+    wl = W.WORKLOADS[name](band_bins=100)
+    gas = avm.Gas(wl.gas, 0)
+    field = avm.Field(wl.field, 0)
+    prim = torch.from_numpy(wl.primaries.view(np.uint8).copy()).to("cuda:0")
+    r = avm.Run(gas, field, prim, wl.n_aval, seed=wl.seed, precision=precision, majorant=avm.BANDED,
+                mode=avm.BATCHED, capacity=CAPACITY[name], timeout_s=300.0, stream=stream, graph=True,
+                band_lookahead=BAND_LOOKAHEAD)
+    for _ in range(warmup):
+        r.execute()
+        r.sync()
+    torch.cuda.synchronize()
+    kms = []
+    t = time.perf_counter()
+    for _ in range(steps):
+        r.execute()
+        r.sync()
+        r.avalanche_counts()
+        kms.append(r.timing()[0])
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t) * 1e3 / steps
+    c = r.counts()
+    r.close()
+    k_ms = sum(kms) / len(kms)
+    polar_b = name == "wire"
+    ops = lane_ops(c, polar_b)
+    flights = c["n_real"] + c["n_null"] + c["n_masked"] + c["n_band"]
+    return {"workload": f"{wl.name}: {wl.description}", "avalanches": wl.n_aval,
+            "precision": "fp32-mixed" if precision == avm.FP32_MIXED else "fp64",
+            "real_collisions_per_s": c["n_real"] / (ms * 1e-3),
+            "secondaries_per_s": c["n_ion"] / (ms * 1e-3), "flights_per_s": flights / (ms * 1e-3),
+            "ms_per_step": ms, "kernel_ms": k_ms, "steps": steps, "warmup": warmup,
+            "electrons_per_step": c["n_endpoints"], "mean_gain": c["n_endpoints"] / wl.n_aval,
+            "roofline": {"bound": "alu", "achieved": ops / (k_ms * 1e-3), "peak": PEAK_LANE_OPS,
+                         "unit": "lane-ops/s", "frac": ops / (k_ms * 1e-3) / PEAK_LANE_OPS,
+                         "traffic": None, "ops_per_launch": ops,
+                         "kernel": "k_persistent<%s,banded,%s>" % (
+                             "float" if precision == avm.FP32_MIXED else "double",
+                             "polar" if polar_b else "slab")}}
+
+
+def crossover_rows(sizes):
     """Wall time of one whole simulation against the number of avalanches
     (argon-like gas, one primary each): the GPU (batched, banded, FP64,
     primaries handed over in host memory, from execute to sync) against the
-    oracle on every host core; the paper reports where the GPU overtakes the
-    CPU (Sec. 4).  Prints one JSON line (not the benchmark line)."""
+    oracle on every host core (the paper's run-mode switch between CPU and
+    GPU rests on where one overtakes the other, Sec. 3.2 and Sec. 4)."""
     import numpy as np
     import torch
 
     from oracle import oracle as O
     from paper_2509_15377_amd import avm, workloads as W
 
-    full = W.argon(1024, band_bins=100)
+    full = W.argon(max(sizes), band_bins=100)
     gas = avm.Gas(full.gas, 0)
     field = avm.Field(full.field, 0)
     og = O.Gas(full.gas, band_bins=100)
     of = O.Field(full.field)
     rows = []
-    for n in (1, 2, 4, 8, 16, 32, 64, 128, 256, 512, 1024):
+    for n in sizes:
         prim = full.primaries[:n]
         r = avm.Run(gas, field, prim, n, seed=full.seed, majorant=avm.BANDED, capacity=20_000_000,
                     timeout_s=120.0, band_lookahead=BAND_LOOKAHEAD)
@@ -148,14 +210,34 @@ def crossover():
             t0 = time.perf_counter()
             r.execute()
             r.sync()
+            r.avalanche_counts()
             ts.append(time.perf_counter() - t0)
         electrons = r.counts()["n_endpoints"]
         r.close()
         t1 = time.perf_counter()
-        O.run(og, of, prim, full.seed, banded=True, band_lookahead=BAND_LOOKAHEAD)
+        _, threads = O.run(og, of, prim, full.seed, banded=True, band_lookahead=BAND_LOOKAHEAD,
+                           return_threads=True)
         tc = time.perf_counter() - t1
         rows.append({"avalanches": n, "electrons": int(electrons), "gpu_s": float(np.median(ts)),
-                     "oracle_s": tc})
+                     "oracle_s": tc, "oracle_threads": int(threads)})
+    return rows
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def crossover():
+    """--crossover: the crossover table alone, at more sizes (not the
+    benchmark line)."""
+    rows = crossover_rows((1, 2, 4, 8, 16, 32, 64, 128, 256, 512, 1024))
     cross = next((r["avalanches"] for r in rows if r["gpu_s"] < r["oracle_s"]), None)
     print(json.dumps({"crossover": rows, "gpu_faster_from_avalanches": cross}), flush=True)
 
@@ -169,6 +251,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-mode reference leg")
     ap.add_argument("--no-mixed", action="store_true", help="skip the FP32-mixed leg")
+    ap.add_argument("--no-workloads", action="store_true",
+                    help="skip the legs of the other workloads (8192 avalanches, high gain, wire)")
     ap.add_argument("--eager", action="store_true",
                     help="launch the batched run eagerly instead of replaying its HIP graph")
     ap.add_argument("--headline-only", action="store_true",
@@ -193,7 +277,7 @@ def main():
         crossover()
         return
     if args.headline_only:
-        args.no_mixed = args.no_plain = args.no_cpu = True
+        args.no_mixed = args.no_plain = args.no_cpu = args.no_workloads = True
     if args.workload != "argon":
         args.no_plain = True  # the generation loop on the global majorant: minutes
     import numpy as np
@@ -229,6 +313,7 @@ def main():
         for _ in range(args.steps):
             run.execute()
             run.sync()
+            run.avalanche_counts()  # the per-avalanche statistics come back in the step
             kms.append(run.timing()[0])
         torch.cuda.synchronize()
         return time.perf_counter() - t, kms
@@ -240,7 +325,7 @@ def main():
     ms_step = wall * 1e3 / args.steps
     value = c["n_real"] / (ms_step * 1e-3)
     k_ms = sum(kernel_ms) / len(kernel_ms)
-    ops = flights * OPS_PER_FLIGHT + c["n_real"] * OPS_PER_REAL + c["n_ion"] * OPS_PER_ION
+    ops = lane_ops(c, args.workload == "wire")
     achieved = ops / (k_ms * 1e-3)
 
     paths = {"batched_fp64_banded": {"real_collisions_per_s": value,
@@ -260,7 +345,8 @@ def main():
             "secondaries_per_s": mc["n_ion"] / (mms * 1e-3),
             "flights_per_s": (mc["n_real"] + mc["n_null"] + mc["n_masked"] + mc["n_band"]) / (mms * 1e-3),
             "ms_per_step": mms, "kernel_ms": sum(mk) / len(mk),
-            "mean_gain": mc["n_endpoints"] / wl.n_aval, "graph": use_graph}
+            "mean_gain": mc["n_endpoints"] / wl.n_aval, "graph": use_graph,
+            "roofline_frac": lane_ops(mc, args.workload == "wire") / (sum(mk) / len(mk) * 1e-3) / PEAK_LANE_OPS}
         mr.close()
     if not args.headline_only and args.workload == "argon":
         side_legs(args, make, timed, paths, gas, field, wl, capacity, stream)
@@ -281,6 +367,17 @@ def main():
                                       "ms_per_step": tp * 1e3, "kernel_ms": pk, "iterations": it}
         pr.close()
 
+    run.close()
+    if not args.no_workloads and args.workload == "argon":
+        # the other workloads, each in FP64 and FP32-mixed with its own
+        # roofline (one warm-up and two timed steps each)
+        legs = []
+        for name in ("batched", "highgain", "wire"):
+            for prec in (avm.FP64, avm.FP32_MIXED):
+                legs.append(workload_leg(name, prec, 2, 1, stream))
+                torch.cuda.empty_cache()
+        paths["workloads"] = legs
+
     cpu = None
     if not args.no_cpu:
         # the oracle on the host cores: the whole workload on every core,
@@ -300,13 +397,22 @@ def main():
                     band_lookahead=BAND_LOOKAHEAD)
         t1c = time.perf_counter() - t3
         cpu = {"value": float(ep["n_real"].sum() / tc), "unit": "real collisions/s",
-               "cores": int(threads), "kind": "oracle",
+               "cores": int(threads), "kind": "oracle", "cpu_model": cpu_model(),
                "sample": (f"all {wl.n_aval} avalanches" if mod == 1 else
                           f"avalanches with id % {mod} == 0 ({sel.size} of {wl.n_aval})")
                          + f", banded majorant, FP64, {tc:.1f} s on {threads} threads",
                "secondaries_per_s": float(ep["n_ion"].sum() / tc),
                "single_thread": {"value": float(ep1["n_real"].sum() / t1c),
                                  "sample": f"avalanches with id % {20 * mod} == 0 ({idx.size}), {t1c:.1f} s"}}
+        if args.workload == "argon":
+            rows = crossover_rows((1, 4, 16, 64, 256))
+            cpu["crossover"] = {
+                "rows": rows,
+                "gpu_faster_from_avalanches": next((r["avalanches"] for r in rows
+                                                    if r["gpu_s"] < r["oracle_s"]), None),
+                "what": "one whole simulation of n avalanches (argon-like gas, one primary each): "
+                        "GPU from execute to sync with host primaries, against the oracle on every "
+                        "host core"}
 
     line = {
         "metric": "electron real collisions/s (secondaries/s alongside) at gain ~1e3",
@@ -326,6 +432,11 @@ def main():
                    "path": "batched persistent kernel, banded majorant (100 bins/band, "
                            f"lookahead {BAND_LOOKAHEAD:g} mean free time), FP64, graph replay",
                    "seed": wl.seed},
+        "timed_region": "execute to sync of the whole run replayed from its HIP graph (reset, "
+                        "primary load from HBM, transport with its in-kernel statistics, totals "
+                        "back to the host), then the per-avalanche statistics copied to the host; "
+                        "primaries resident in HBM before the region (their PCIe copy inside "
+                        "every step: paths.batched_fp64_banded_host_primaries)",
         "secondaries_per_s": c["n_ion"] / (ms_step * 1e-3),
         "flights_per_s": flights / (ms_step * 1e-3),
         "null_fraction": (c["n_null"] + c["n_masked"]) / max(flights, 1),
@@ -337,7 +448,6 @@ def main():
                      "ops_per_launch": ops},
         "cpu_baseline": cpu,
     }
-    run.close()
     print(json.dumps(line), flush=True)
 
 

@@ -232,19 +232,13 @@ AVM_FN void write_start(const Store& S, uint64_t s, const Elec<R>& parent, const
 // the eight counters of AvalStats, then the status histogram.
 constexpr int kTally = 17;
 
-// Sum of v over the wave's lanes, as a wave-uniform (scalar) value.
-AVM_FN uint32_t wave_sum32(uint32_t v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  return __builtin_amdgcn_readlane(v, 0);
-}
+// Wave-wide sum (the device library's DPP reduction: row shifts and
+// broadcasts, no LDS round trips).
+extern "C" __device__ __attribute__((const)) unsigned long long __ockl_wfred_add_u64(unsigned long long);
 
-// Sum of v over the lanes with `in` (counts below 2^30 each): in 32 bits
-// when every term is below 2^25, else in two 16-bit halves.
+// Sum of v over the lanes with `in` (every lane of the wave calls it).
 AVM_FN unsigned long long group_sum(bool in, uint32_t v) {
-  const uint32_t x = in ? v : 0u;
-  if (__ballot(x >> 25) == 0) return wave_sum32(x);
-  return ((unsigned long long)wave_sum32(x >> 16) << 16) + wave_sum32(x & 0xFFFFu);
+  return __ockl_wfred_add_u64(in ? (unsigned long long)v : 0ull);
 }
 
 // Adds one counter of a group of lanes to its avalanche (device atomic) and

@@ -130,6 +130,35 @@ def test_wire_polar_map_with_b(A, oracle_mod):
     assert tot["n_status"][7] > 0 and tot["n_real"] > 0
 
 
+@pytest.mark.parametrize("majorant", ["global", "banded"])
+def test_wire_crossed_map_per_trajectory(A, oracle_mod, majorant):
+    """A polar map that depends on the azimuth and has E_phi != 0 (the wire
+    field plus 500 V/cm along x, 0.5 T): the device's azimuthal weights,
+    periodic wrap and E_phi rotation against the oracle's (which are pinned
+    to the closed form in test_oracle_polar_map.py), per trajectory on a
+    bounded horizon (rounding differences grow in this geometry), with the
+    global majorant and with the helical band bound."""
+    wl = W.wire_crossed(24)
+    prim = wl.primaries.copy()
+    # four of them next to the periodic seam phi = 0 = 2 pi
+    seam = np.array([-0.01, -0.001, 0.001, 0.01])
+    prim["x"][:4], prim["y"][:4] = 0.1 * np.cos(seam), 0.1 * np.sin(seam)
+    if majorant == "global":
+        ref = oracle_mod.run(wl.gas, wl.field, prim, wl.seed, k_max=20000)
+        ep, tot, _ = A.run(wl, primaries=prim, capacity=2_000_000, k_max=20000)
+    else:
+        og = oracle_mod.Gas(wl.gas, band_bins=100)
+        ref = oracle_mod.run(og, wl.field, prim, wl.seed, banded=True, k_max=600)
+        ep, tot, _ = A.run(wl, primaries=prim, band_bins=100, majorant=A.BANDED, capacity=2_000_000,
+                           k_max=600)
+    rep = CMP.assert_parity(ep, ref)
+    print("wire crossed", majorant, rep)
+    # the azimuth matters: the electrons' final azimuths cover the circle
+    phi = np.arctan2(ep["y1"], ep["x1"])
+    assert np.histogram(phi, bins=4, range=(-np.pi, np.pi))[0].min() > 0
+    assert tot["n_status"][7] > 0
+
+
 def test_full_argon_bench_configuration_sampled(A, oracle_mod):
     """The benchmark's launch configuration (1000 avalanches, batched,
     banded with lookahead 1, FP64, graph replay) checked on every 50th

@@ -8,6 +8,7 @@ import numpy as np
 import pytest
 from scipy import stats
 
+from gates import statistical_gates
 from oracle import compare as CMP
 from paper_2509_15377_amd import workloads as W
 
@@ -125,3 +126,17 @@ def test_highgain_fp32_statistics(highgain_pair):
     att32 = np.bincount(e32["aval"][e32["status"] == 3], minlength=wl.n_aval)
     eff64, eff32 = (g64 - att64).mean(), (g32 - att32).mean()
     assert abs(eff32 - eff64) / eff64 < 0.01
+
+
+def test_highgain_fp32_against_oracle_subset(highgain_pair, oracle_mod):
+    """High gain with attachment: every 32nd avalanche (8 of them, ~1e6
+    electrons) of the FP32-mixed run against the FP64 oracle on the same
+    avalanches, with the accuracy gates (the per-avalanche KS tests have
+    only 8 samples each, so the pooled ones carry the weight)."""
+    wl, _, (e32, t32, _) = highgain_pair
+    idx = W.subset_primaries(wl.primaries, 32)
+    ref = oracle_mod.run(oracle_mod.Gas(wl.gas, band_bins=100), wl.field, wl.primaries[idx], wl.seed,
+                         banded=True, ids=idx)
+    sub = e32[(e32["aval"] % 32) == 0]
+    assert (sub["status"] == 3).any() and (ref["status"] == 3).any()
+    statistical_gates(ref, sub, "highgain fp32 vs oracle (every 32nd avalanche)", wl.n_aval)
