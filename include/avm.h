@@ -290,6 +290,13 @@ typedef struct {
 } avm_endpoint_arrays;
 avm_status avm_run_endpoint_arrays(const avm_run* run, avm_endpoint_arrays* out);
 
+/* Sec. 3.3 (each event of a validation run draws its own random numbers).
+ * The seed of the following executes: the same primaries and options with
+ * other random streams, without a new run (a captured graph is captured
+ * again on the next execute).  Results of the last execute are no longer
+ * available.  Errors: AVM_E_ARG for a NULL run; AVM_E_STATE while the run
+ * executes. */
+avm_status avm_run_set_seed(avm_run* run, uint64_t seed);
 /* Sec. 4 (the GPU run time measured against the CPU run).
  * Kernel time of the last execute (ms, HIP events on the run's stream
  * around the transport kernels; plain mode: summed over iterations; graph

@@ -129,6 +129,7 @@ _SIGS = {
     "avm_run_endpoints": ([_VP, C.c_uint64, C.c_uint64, _VP], C.c_int),
     "avm_run_endpoint_arrays": ([_VP, C.POINTER(_EndpointArrays)], C.c_int),
     "avm_run_timing": ([_VP, _DP, C.POINTER(C.c_uint32)], C.c_int),
+    "avm_run_set_seed": ([_VP, C.c_uint64], C.c_int),
     "avm_run_destroy": ([_VP], None),
     "avm_run_set_signal": ([_VP, C.c_double, C.c_double, C.c_int32], C.c_int),
     "avm_run_signal": ([_VP, C.c_uint32, C.c_uint32, _DP], C.c_int),
@@ -388,6 +389,26 @@ class Run:
         _check(lib().avm_run_endpoint_arrays(self.h, C.byref(a)))
         return {name: getattr(a, name) for name, _ in a._fields_}
 
+    def endpoint_tensors(self, fields=None):
+        """The stored endpoints as torch tensors on the device, without a
+        copy (avm_run_endpoint_arrays; valid until the run is closed or
+        executed again): a dict of 1-D tensors of num_endpoints() entries."""
+        import torch
+        n = self.num_endpoints()
+        ptrs = self.endpoint_arrays()
+        # unsigned fields come back as signed tensors of the same bits
+        typestrs = {"f8": "<f8", "u8": "<i8", "u4": "<i4"}
+        out = {}
+        for name, k in _NOALLOC_ARRAYS:
+            if fields is not None and name not in fields:
+                continue
+
+            class _View:
+                __cuda_array_interface__ = {"shape": (n,), "typestr": typestrs[k],
+                                            "data": (ptrs[name] or 0, False), "version": 2}
+            out[name] = torch.as_tensor(_View(), device="cuda")
+        return out
+
     def set_signal(self, t0_ns: float, dt_ns: float, n_bins: int):
         """Request the induced signal on the readout electrode (avm_run_set_signal)."""
         _check(lib().avm_run_set_signal(self.h, float(t0_ns), float(dt_ns), int(n_bins)),
@@ -399,6 +420,10 @@ class Run:
         out = np.zeros((self.n_aval, self.n_signal_bins))
         _check(lib().avm_run_signal(self.h, 0, self.n_aval, out.ctypes.data_as(_DP)), "avm_run_signal")
         return out
+
+    def set_seed(self, seed: int):
+        """The seed of the following executes (avm_run_set_seed)."""
+        _check(lib().avm_run_set_seed(self.h, int(seed)), "avm_run_set_seed")
 
     def timing(self):
         ms = C.c_double()

@@ -1057,6 +1057,24 @@ avm_status avm_run_signal(const avm_run* r, uint32_t first, uint32_t n, double* 
   return AVM_OK;
 }
 
+avm_status avm_run_set_seed(avm_run* r, uint64_t seed) {
+  g_err.clear();
+  if (!r) return fail(AVM_E_ARG, "avm_run_set_seed: run is NULL");
+  if (r->executed && !r->synced) return fail(AVM_E_STATE, "avm_run_set_seed: the run is executing");
+  if (r->opts.seed == seed) return AVM_OK;
+  r->opts.seed = seed;
+  if (r->graph_exec) {  // captured with the old seed in the kernel arguments
+    DeviceGuard dg(r->gas->device);
+    (void)hipGraphExecDestroy(r->graph_exec);
+    (void)hipGraphDestroy(r->graph);
+    r->graph_exec = nullptr;
+    r->graph = nullptr;
+  }
+  r->synced = 0;
+  r->executed = 0;
+  return AVM_OK;
+}
+
 avm_status avm_run_timing(const avm_run* r, double* transport_ms, uint32_t* iterations) {
   if (!r) return fail(AVM_E_ARG, "avm_run_timing: run is NULL");
   if (!r->synced) return fail(AVM_E_STATE, "avm_run_timing: call avm_run_sync first");

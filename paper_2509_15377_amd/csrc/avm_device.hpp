@@ -440,8 +440,6 @@ template <> struct M<double> {
   AVM_FN static double tan_(double x) { return tan(x); }
   AVM_FN static double atan_(double x) { return atan(x); }
   AVM_FN static void sincospi_(double x, double* s, double* c) { sincospi_pos(x, s, c); }
-  AVM_FN static void sincos_(double x, double* s, double* c) { sincos(x, s, c); }
-  AVM_FN static double sin_(double x) { return sin(x); }
   AVM_FN static double abs_(double x) { return fabs(x); }
   AVM_FN static double inf() { return __builtin_inf(); }
 };
@@ -455,8 +453,6 @@ template <> struct M<float> {
   AVM_FN static float tan_(float x) { return tanf(x); }
   AVM_FN static float atan_(float x) { return atanf(x); }
   AVM_FN static void sincospi_(float x, float* s, float* c) { sincospif(x, s, c); }
-  AVM_FN static void sincos_(float x, float* s, float* c) { sincosf(x, s, c); }
-  AVM_FN static float sin_(float x) { return sinf(x); }
   AVM_FN static float abs_(float x) { return fabsf(x); }
   AVM_FN static float inf() { return __builtin_inff(); }
 };
@@ -811,11 +807,15 @@ AVM_FN void propagate(const FieldDev& F, const Elec<R>& e, R ax, R ay, R az, R E
   const R cx = by * u0z - bz * u0y;
   const R cy = bz * u0x - bx * u0z;
   const R cz = bx * u0y - by * u0x;
+  // sin and cos of the phase ph = omega s, and 1 - cos(ph) without
+  // cancellation, from one sin/cos pair of the half phase:
+  // sin(ph) = 2 sh ch, 1 - cos(ph) = 2 sh^2 (sh, ch of ph / 2)
   const R ph = (R)F.omega * s;
-  R sn, cs;
-  Mr::sincos_(ph, &sn, &cs);
-  const R sh = Mr::sin_(R(0.5) * ph);
+  R sh, ch;
+  Mr::sincospi_(ph * R(0.15915494309189535), &sh, &ch);
+  const R sn = R(2) * sh * ch;
   const R omc = R(2) * sh * sh;
+  const R cs = R(1) - omc;
   const R along = vpar * s + R(0.5) * apar * s * s;
   const R io = (R)F.inv_omega;
   const R a1 = sn * io, a2 = omc * io;

@@ -97,6 +97,7 @@ def test_argument_errors_without_a_device(A):
     assert L.avm_gas_set_penning(None, 1, 0.5, 1.0) == A.AVM_E_ARG
     assert L.avm_run_set_signal(None, 0.0, 0.01, 10) == A.AVM_E_ARG
     assert L.avm_run_signal(None, 0, 0, None) == A.AVM_E_ARG
+    assert L.avm_run_set_seed(None, 1) == A.AVM_E_ARG
     res = A._TuneResult()
     assert L.avm_autotune(None, None, None, 0, 0, 0, C.byref(o), 0, None, C.byref(res)) == A.AVM_E_ARG
     L.avm_gas_destroy(None)
