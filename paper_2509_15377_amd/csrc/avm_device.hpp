@@ -1202,19 +1202,43 @@ AVM_FN int32_t flight_step(Elec<R>& e, const GasDev& G, const TV& T, const Field
     propagate<R, kMayHaveB>(F, e, ax, ay, az, Ex, Ey, Ez, tau_end, rx, ry, rz, ux, uy, uz);
     const double r2 = rx * rx + ry * ry;
     if (r2 <= F.a2 || r2 >= F.b2) {
-      // bisection on the inside/outside predicate (excursions that leave
-      // and re-enter within one flight are not detected)
+      // the time the boundary is crossed, between the flight start (inside)
+      // and its end (outside): a bracket [lo, hi] on the inside/outside
+      // predicate, shrunk at false-position points of
+      // g(s) = R^2 - rho(s)^2 (wire) or rho(s)^2 - R^2 (tube), negative
+      // inside, with the Illinois halving of the stale end's value, and at
+      // the midpoint when the interpolant leaves the bracket; it stops when
+      // the bracket is a few ulps wide (excursions that leave and re-enter
+      // within one flight are not detected)
+      const bool to_wire = r2 <= F.a2;
+      const double R2 = to_wire ? F.a2 : F.b2;
+      const double sg = to_wire ? -1.0 : 1.0;
+      const double q0 = e.x * e.x + e.y * e.y;
       double lo = 0.0, hi = (double)tau_end;
-      for (int it = 0; it < 60; ++it) {
-        const double mid = 0.5 * (lo + hi);
+      double glo = sg * (q0 - R2), ghi = sg * (r2 - R2);
+      int last = 0;
+      // a few ulps of the flight time in the step's precision (the trial
+      // times are rounded to R for the flight formula)
+      const double eps = sizeof(R) == 4 ? 2.4e-7 : 4.5e-16;
+      for (int it = 0; it < 60 && hi - lo > eps * hi; ++it) {
+        double c = (lo * ghi - hi * glo) / (ghi - glo);
+        if (!(c > lo && c < hi)) c = 0.5 * (lo + hi);
         double mx, my, mz;
         R wx_, wy_, wz_;
-        propagate<R, kMayHaveB>(F, e, ax, ay, az, Ex, Ey, Ez, (R)mid, mx, my, mz, wx_, wy_, wz_);
+        propagate<R, kMayHaveB>(F, e, ax, ay, az, Ex, Ey, Ez, (R)c, mx, my, mz, wx_, wy_, wz_);
         const double m2 = mx * mx + my * my;
-        if (m2 <= F.a2 || m2 >= F.b2)
-          hi = mid;
-        else
-          lo = mid;
+        const double gc = sg * (m2 - R2);
+        if (m2 <= F.a2 || m2 >= F.b2) {
+          hi = c;
+          ghi = gc > 0.0 ? gc : 0.0;
+          if (last < 0) glo *= 0.5;
+          last = -1;
+        } else {
+          lo = c;
+          glo = gc < 0.0 ? gc : -0.0;
+          if (last > 0) ghi *= 0.5;
+          last = 1;
+        }
       }
       s_exit = hi;
       propagate<R, kMayHaveB>(F, e, ax, ay, az, Ex, Ey, Ez, (R)s_exit, rx, ry, rz, ux, uy, uz);
