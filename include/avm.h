@@ -34,7 +34,7 @@
 extern "C" {
 #endif
 
-#define AVM_ABI_VERSION 2
+#define AVM_ABI_VERSION 3
 
 typedef enum {
   AVM_OK = 0,
@@ -280,13 +280,23 @@ avm_status avm_run_num_endpoints(const avm_run* run, uint64_t* n);
 /* Copy endpoints [first, first+n) in storage order to host memory. */
 avm_status avm_run_endpoints(const avm_run* run, uint64_t first, uint64_t n, avm_endpoint* out);
 
-/* Device pointers to the endpoint arrays (structure of arrays, indexed by
- * storage slot, valid until avm_run_destroy). */
+/* The end of one electron (written once, when it terminates): position,
+ * time and energy, status, counters and decision trace, as in
+ * avm_endpoint.  Kept as one record per electron so that a termination
+ * writes 72 contiguous bytes. */
 typedef struct {
-  const double *x0, *y0, *z0, *t0, *e0, *x1, *y1, *z1, *t1, *e1;
+  double x1, y1, z1, t1, e1;
+  uint32_t status, n_real, n_ion, n_null, n_masked, n_band, n_overflow, trace;
+} avm_end_record; /* 72 bytes */
+
+/* Device pointers to the endpoints, indexed by storage slot, valid until
+ * avm_run_destroy: the start of each electron as arrays (structure of
+ * arrays, written when it is created), its end as records. */
+typedef struct {
+  const double *x0, *y0, *z0, *t0, *e0;
   const uint64_t *eid, *parent;
-  const uint32_t *avalanche, *status, *n_real, *n_ion, *n_null, *n_masked, *n_band, *n_overflow;
-  const uint32_t* trace;
+  const uint32_t* avalanche;
+  const avm_end_record* end;
 } avm_endpoint_arrays;
 avm_status avm_run_endpoint_arrays(const avm_run* run, avm_endpoint_arrays* out);
 
@@ -394,10 +404,10 @@ avm_status avm_autotune(avm_gas* gas, const avm_field* field, const avm_primary*
  *   AVM_NOALLOC_MAX_ELECTRONS, and >= n_prim); hip_stream is where the work
  *   is enqueued; timeout_s bounds the transport kernel on the device (the
  *   flag AVM_NOALLOC_TIMEOUT), nothing waits on the host.
- * out: device pointers, caller-owned.  The per-electron arrays are indexed
- *   by storage slot as in avm_endpoint_arrays (slots [0, min(n_requested,
- *   capacity)) are written); aval_counts [n_aval][8] receives the
- *   per-avalanche counters (endpoints, ionisations, attachments, real,
+ * out: device pointers, caller-owned.  The per-electron arrays and end
+ *   records are indexed by storage slot as in avm_endpoint_arrays (slots
+ *   [0, min(n_requested, capacity)) are written); aval_counts [n_aval][8]
+ *   receives the per-avalanche counters (endpoints, ionisations, attachments, real,
  *   null, masked, band cuts, overflows) and is cleared first; counts
  *   receives one avm_counts record of totals, flags one word of
  *   AVM_NOALLOC_* bits.
@@ -412,10 +422,10 @@ avm_status avm_autotune(avm_gas* gas, const avm_field* field, const avm_primary*
 #define AVM_NOALLOC_TRUNCATED 4u      /* electrons beyond capacity were dropped           */
 
 typedef struct {
-  double *x0, *y0, *z0, *t0, *e0, *x1, *y1, *z1, *t1, *e1;
+  double *x0, *y0, *z0, *t0, *e0;
   uint64_t *eid, *parent;
-  uint32_t *avalanche, *status, *n_real, *n_ion, *n_null, *n_masked, *n_band, *n_overflow;
-  uint32_t* trace;
+  uint32_t* avalanche;
+  avm_end_record* end;   /* [capacity]                         */
   uint64_t* aval_counts; /* [n_aval][8]                       */
   avm_counts* counts;    /* one record                         */
   uint32_t* flags;       /* one word of AVM_NOALLOC_* bits     */

@@ -80,24 +80,32 @@ class _TuneResult(C.Structure):
 TUNE_BANDS = 1
 
 
+# The start of each electron is stored as arrays (name, numpy kind); its end
+# as one avm_end_record of 72 bytes (name, numpy kind, byte offset).
+_START_ARRAYS = (("x0", "f8"), ("y0", "f8"), ("z0", "f8"), ("t0", "f8"), ("e0", "f8"),
+                 ("eid", "u8"), ("parent", "u8"), ("avalanche", "u4"))
+END_RECORD_DTYPE = np.dtype([
+    ("x1", "<f8"), ("y1", "<f8"), ("z1", "<f8"), ("t1", "<f8"), ("e1", "<f8"),
+    ("status", "<u4"), ("n_real", "<u4"), ("n_ion", "<u4"), ("n_null", "<u4"),
+    ("n_masked", "<u4"), ("n_band", "<u4"), ("n_overflow", "<u4"), ("trace", "<u4"),
+])
+assert END_RECORD_DTYPE.itemsize == 72
+_END_FIELDS = tuple((n, END_RECORD_DTYPE[n].str[1:], END_RECORD_DTYPE.fields[n][1])
+                    for n in END_RECORD_DTYPE.names)
+
+
 class _EndpointArrays(C.Structure):
-    _fields_ = [(n, C.c_void_p) for n in ("x0", "y0", "z0", "t0", "e0", "x1", "y1", "z1", "t1", "e1",
-                                          "eid", "parent", "avalanche", "status", "n_real", "n_ion",
-                                          "n_null", "n_masked", "n_band", "n_overflow", "trace")]
+    _fields_ = [(n, C.c_void_p) for n, _ in _START_ARRAYS] + [("end", C.c_void_p)]
 
 
 NOALLOC_MAX_ELECTRONS = 4194304
 NOALLOC_TIMEOUT, NOALLOC_BAD_AVALANCHE, NOALLOC_TRUNCATED = 1, 2, 4
-_NOALLOC_ARRAYS = (("x0", "f8"), ("y0", "f8"), ("z0", "f8"), ("t0", "f8"), ("e0", "f8"),
-                   ("x1", "f8"), ("y1", "f8"), ("z1", "f8"), ("t1", "f8"), ("e1", "f8"),
-                   ("eid", "u8"), ("parent", "u8"), ("avalanche", "u4"), ("status", "u4"),
-                   ("n_real", "u4"), ("n_ion", "u4"), ("n_null", "u4"), ("n_masked", "u4"),
-                   ("n_band", "u4"), ("n_overflow", "u4"), ("trace", "u4"))
 
 
 class _NoallocOut(C.Structure):
-    _fields_ = [(n, C.c_void_p) for n, _ in _NOALLOC_ARRAYS] + [
-        ("aval_counts", C.c_void_p), ("counts", C.c_void_p), ("flags", C.c_void_p)]
+    _fields_ = [(n, C.c_void_p) for n, _ in _START_ARRAYS] + [
+        ("end", C.c_void_p), ("aval_counts", C.c_void_p), ("counts", C.c_void_p),
+        ("flags", C.c_void_p)]
 
 
 # C entry points: name -> (argtypes, restype)
@@ -396,16 +404,22 @@ class Run:
         import torch
         n = self.num_endpoints()
         ptrs = self.endpoint_arrays()
-        # unsigned fields come back as signed tensors of the same bits
+        # unsigned fields come back as signed tensors of the same bits; the
+        # end fields are strided views into the 72-byte end records
         typestrs = {"f8": "<f8", "u8": "<i8", "u4": "<i4"}
+        views = [(name, k, ptrs[name] or 0, None) for name, k in _START_ARRAYS]
+        views += [(name, k, (ptrs["end"] or 0) + off, (END_RECORD_DTYPE.itemsize,))
+                  for name, k, off in _END_FIELDS]
         out = {}
-        for name, k in _NOALLOC_ARRAYS:
+        for name, k, ptr, strides in views:
             if fields is not None and name not in fields:
                 continue
+            cai = {"shape": (n,), "typestr": typestrs[k], "data": (ptr, False), "version": 2}
+            if strides is not None:
+                cai["strides"] = strides
 
             class _View:
-                __cuda_array_interface__ = {"shape": (n,), "typestr": typestrs[k],
-                                            "data": (ptrs[name] or 0, False), "version": 2}
+                __cuda_array_interface__ = cai
             out[name] = torch.as_tensor(_View(), device="cuda")
         return out
 
@@ -448,7 +462,8 @@ def noalloc_outputs(capacity: int, n_aval: int, device="cuda:0"):
     here, by torch, before the call)."""
     import torch
     dt = {"f8": torch.float64, "u8": torch.int64, "u4": torch.int32}
-    out = {n: torch.zeros(capacity, dtype=dt[k], device=device) for n, k in _NOALLOC_ARRAYS}
+    out = {n: torch.zeros(capacity, dtype=dt[k], device=device) for n, k in _START_ARRAYS}
+    out["end"] = torch.zeros((capacity, END_RECORD_DTYPE.itemsize), dtype=torch.uint8, device=device)
     out["aval_counts"] = torch.zeros((max(n_aval, 1), 8), dtype=torch.int64, device=device)
     out["counts"] = torch.zeros(C.sizeof(_Counts), dtype=torch.uint8, device=device)
     out["flags"] = torch.zeros(1, dtype=torch.int32, device=device)
@@ -468,9 +483,11 @@ def run_noalloc(gas: Gas, field: Field, primaries, n_aval: int, out: dict, *, se
     cap = out["x0"].numel()
     o = _make_opts(seed, precision, majorant, BATCHED, flights_per_pass, t_max, cap, k_max,
                    waves_per_cu, timeout_s, stream, False, band_lookahead)
-    st = _NoallocOut(*[C.c_void_p(out[n].data_ptr()) for n, _ in _NOALLOC_ARRAYS],
-                     C.c_void_p(out["aval_counts"].data_ptr()), C.c_void_p(out["counts"].data_ptr()),
-                     C.c_void_p(out["flags"].data_ptr()))
+    if out["end"].numel() != cap * END_RECORD_DTYPE.itemsize:
+        raise ValueError("run_noalloc: out['end'] must hold one 72-byte record per slot")
+    st = _NoallocOut(*[C.c_void_p(out[n].data_ptr()) for n, _ in _START_ARRAYS],
+                     C.c_void_p(out["end"].data_ptr()), C.c_void_p(out["aval_counts"].data_ptr()),
+                     C.c_void_p(out["counts"].data_ptr()), C.c_void_p(out["flags"].data_ptr()))
     _check(lib().avm_run_noalloc(gas.h, field.h, ptr, n_prim, int(n_aval), C.byref(o), C.byref(st)),
            "avm_run_noalloc")
     del keep
@@ -483,9 +500,12 @@ def noalloc_results(out: dict, n_aval: int):
     tot = _counts_dict(c)
     n = min(tot["n_requested"], out["x0"].numel())
     ep = np.zeros(n, dtype=ENDPOINT_DTYPE)
-    names = {"avalanche": "aval", "n_overflow": "n_overflow"}
-    for name, _ in _NOALLOC_ARRAYS:
+    names = {"avalanche": "aval"}
+    for name, _ in _START_ARRAYS:
         ep[names.get(name, name)] = out[name][:n].cpu().numpy().view(ENDPOINT_DTYPE[names.get(name, name)])
+    end = out["end"][:n].cpu().numpy().reshape(-1).view(END_RECORD_DTYPE)
+    for name in END_RECORD_DTYPE.names:
+        ep[name] = end[name]
     ep = ep[np.lexsort((ep["eid"], ep["aval"]))]
     ac = out["aval_counts"][:n_aval].cpu().numpy().view(np.uint64).astype(np.int64)
     keys = ("n_endpoints", "n_ion", "n_att", "n_real", "n_null", "n_masked", "n_band", "n_overflow")

@@ -599,11 +599,9 @@ static size_t layout_store(Store& S, char* base, uint64_t cap) {
   take(&S.x0, 8); take(&S.y0, 8); take(&S.z0, 8); take(&S.t0, 8);
   take(&S.vx0, 8); take(&S.vy0, 8); take(&S.vz0, 8); take(&S.e0, 8);
   take(&S.eid, 8); take(&S.parent, 8); take(&S.aval, 4); take(&S.qready, 4); take(&S.qslot, 4);
-  take(&S.x1, 8); take(&S.y1, 8); take(&S.z1, 8); take(&S.t1, 8); take(&S.e1, 8);
+  take(&S.end, sizeof(avm_end_record));
   take(&S.vx1, 8); take(&S.vy1, 8); take(&S.vz1, 8);
   take(&S.k1, 4); take(&S.band1, 4);
-  take(&S.status, 4); take(&S.n_real, 4); take(&S.n_ion, 4); take(&S.n_null, 4);
-  take(&S.n_masked, 4); take(&S.n_band, 4); take(&S.n_over, 4); take(&S.trace, 4);
   S.capacity = cap;
   return off;
 }
@@ -980,14 +978,19 @@ avm_status avm_run_endpoints(const avm_run* r, uint64_t first, uint64_t n, avm_e
 #define AVM_GET(fn, arr, field) \
   if ((s = fn(S.arr, offsetof(avm_endpoint, field))) != AVM_OK) return s
   AVM_GET(getd, x0, x0); AVM_GET(getd, y0, y0); AVM_GET(getd, z0, z0); AVM_GET(getd, t0, t0);
-  AVM_GET(getd, e0, e0); AVM_GET(getd, x1, x1); AVM_GET(getd, y1, y1); AVM_GET(getd, z1, z1);
-  AVM_GET(getd, t1, t1); AVM_GET(getd, e1, e1);
+  AVM_GET(getd, e0, e0);
   AVM_GET(getq, eid, eid); AVM_GET(getq, parent, parent);
-  AVM_GET(getu, aval, avalanche); AVM_GET(getu, status, status); AVM_GET(getu, n_real, n_real);
-  AVM_GET(getu, n_ion, n_ion); AVM_GET(getu, n_null, n_null); AVM_GET(getu, n_masked, n_masked);
-  AVM_GET(getu, n_band, n_band); AVM_GET(getu, n_over, n_overflow);
-  AVM_GET(getu, trace, trace);
+  AVM_GET(getu, aval, avalanche);
 #undef AVM_GET
+  std::vector<avm_end_record> rec(n);
+  HIP_TRY(hipMemcpy(rec.data(), S.end + first, sizeof(avm_end_record) * n, hipMemcpyDeviceToHost));
+  for (uint64_t i = 0; i < n; ++i) {
+    const avm_end_record& c = rec[i];
+    avm_endpoint& o = out[i];
+    o.x1 = c.x1; o.y1 = c.y1; o.z1 = c.z1; o.t1 = c.t1; o.e1 = c.e1;
+    o.status = c.status; o.n_real = c.n_real; o.n_ion = c.n_ion; o.n_null = c.n_null;
+    o.n_masked = c.n_masked; o.n_band = c.n_band; o.n_overflow = c.n_overflow; o.trace = c.trace;
+  }
   return AVM_OK;
 }
 
@@ -995,10 +998,7 @@ avm_status avm_run_endpoint_arrays(const avm_run* r, avm_endpoint_arrays* out) {
   if (!r || !out) return fail(AVM_E_ARG, "avm_run_endpoint_arrays: NULL argument");
   const Store& S = r->S;
   out->x0 = S.x0; out->y0 = S.y0; out->z0 = S.z0; out->t0 = S.t0; out->e0 = S.e0;
-  out->x1 = S.x1; out->y1 = S.y1; out->z1 = S.z1; out->t1 = S.t1; out->e1 = S.e1;
-  out->eid = S.eid; out->parent = S.parent; out->avalanche = S.aval; out->status = S.status;
-  out->n_real = S.n_real; out->n_ion = S.n_ion; out->n_null = S.n_null; out->n_masked = S.n_masked;
-  out->n_band = S.n_band; out->n_overflow = S.n_over; out->trace = S.trace;
+  out->eid = S.eid; out->parent = S.parent; out->avalanche = S.aval; out->end = S.end;
   return AVM_OK;
 }
 

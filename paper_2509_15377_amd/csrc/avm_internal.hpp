@@ -10,6 +10,8 @@
 
 namespace avm {
 
+static_assert(sizeof(avm_end_record) == 72 && alignof(avm_end_record) == 8, "end record layout");
+
 // Per-avalanche statistics (and totals, with the status histogram).
 struct AvalStats {
   unsigned long long c[8];  // endpoints, ionisations, attachments, real, null, masked, band cuts, overflows
@@ -20,11 +22,11 @@ struct Totals {
   unsigned long long _pad[7];
 };
 
-// Device store of a run, structure of arrays indexed by slot.  Slot s holds
-// the s-th electron created: its start record (written when it is created)
-// and its end record (written when it terminates).  The plain mode also
-// keeps the state of live electrons between transport iterations in the end
-// record (x1..t1 = current position, v1 = current velocity).  In device code
+// Device store of a run, indexed by slot.  Slot s holds the s-th electron
+// created: its start record (arrays, written when it is created) and its
+// end record (one 72-byte record, written when it terminates).  The plain
+// mode also keeps the state of live electrons between transport iterations
+// in the end record (x1..t1 = current position) and in vx1..band1.  In device code
 // the pointers are typed as global memory (same 64-bit layout), so accesses
 // are global instructions with a scalar base rather than FLAT ones (only in
 // the translation unit of the kernels, which defines AVM_KERNELS_TU; host
@@ -40,10 +42,11 @@ struct Store {
   AVM_GLB uint32_t* aval;
   AVM_GLB uint32_t* qready;  // batched: queue entry q published when qready[q] == epoch
   AVM_GLB uint32_t* qslot;   // batched: slot of queue entry q
-  AVM_GLB double *x1, *y1, *z1, *t1, *e1, *vx1, *vy1, *vz1;
-  AVM_GLB uint32_t *k1, *band1;
-  AVM_GLB uint32_t *status, *n_real, *n_ion, *n_null, *n_masked, *n_band, *n_over;
-  AVM_GLB uint32_t* trace;  // decision trace (plain mode: running, between iterations)
+  // end records, one per slot (plain mode: also the live position, time,
+  // counters and running decision trace between iterations)
+  AVM_GLB avm_end_record* end;
+  AVM_GLB double *vx1, *vy1, *vz1;  // plain mode: live velocity
+  AVM_GLB uint32_t *k1, *band1;      // plain mode: live flight index and band
   // statistics, added to by the transport kernels as electrons terminate
   AVM_GLB AvalStats* stats;  // [n_aval]
   AVM_GLB Totals* tot;

@@ -177,11 +177,9 @@ __global__ void k_load_primaries(const PrimaryRec* __restrict__ prim, uint64_t n
   S.parent[i] = 0;
   S.aval[i] = a;
   if (plain) {
-    S.x1[i] = p.x; S.y1[i] = p.y; S.z1[i] = p.z; S.t1[i] = p.t;
+    S.end[i] = avm_end_record{p.x, p.y, p.z, p.t, 0.0, 0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
     S.vx1[i] = sp * dx; S.vy1[i] = sp * dy; S.vz1[i] = sp * dz;
     S.k1[i] = 0; S.band1[i] = 0;
-    S.n_real[i] = 0; S.n_ion[i] = 0; S.n_null[i] = 0; S.n_masked[i] = 0;
-    S.n_band[i] = 0; S.n_over[i] = 0; S.status[i] = 0; S.trace[i] = 0;
     active[i] = (uint32_t)i;
   }
   S.qslot[i] = (uint32_t)i;
@@ -204,15 +202,13 @@ AVM_FN uint32_t null_count(const Elec<R>& e, uint32_t status) {
   return e.k - e.n_masked - e.n_band - e.n_real + (status == ST_ATTACHED ? 1u : 0u);
 }
 
+// The end record of a terminated electron: 72 contiguous bytes.
 template <class R>
 AVM_FN void write_end(const Store& S, uint32_t s, const Elec<R>& e, const RunParams& P,
                       uint32_t status) {
-  S.x1[s] = e.x; S.y1[s] = e.y; S.z1[s] = e.z; S.t1[s] = e.t;
-  S.e1[s] = (double)energy<R>(P, e.vx, e.vy, e.vz);
-  S.status[s] = status;
-  S.n_real[s] = e.n_real; S.n_ion[s] = e.n_ion; S.n_null[s] = null_count(e, status);
-  S.n_masked[s] = e.n_masked; S.n_band[s] = e.n_band; S.n_over[s] = e.n_over;
-  S.trace[s] = e.trace;
+  S.end[s] = avm_end_record{e.x, e.y, e.z, e.t, (double)energy<R>(P, e.vx, e.vy, e.vz), status,
+                            e.n_real, e.n_ion, null_count(e, status), e.n_masked, e.n_band, e.n_over,
+                            e.trace};
 }
 
 template <class R>
@@ -340,16 +336,17 @@ __global__ void __launch_bounds__(kBlock) k_generation(GasDev G, FieldDev F, Run
   Child<R> child;
   if (mine) {
     slot = active[i];
-    e.x = S.x1[slot]; e.y = S.y1[slot]; e.z = S.z1[slot]; e.t = S.t1[slot];
+    const avm_end_record live = S.end[slot];
+    e.x = live.x1; e.y = live.y1; e.z = live.z1; e.t = live.t1;
     e.vx = (R)S.vx1[slot]; e.vy = (R)S.vy1[slot]; e.vz = (R)S.vz1[slot];
     e.eid = S.eid[slot];
     e.aval = S.aval[slot];
     e.k = S.k1[slot];
     e.band = kBanded ? (e.k == 0 ? band_of<R>(G, T, energy<R>(P, e.vx, e.vy, e.vz)) : (int32_t)S.band1[slot])
                      : G.n_bands - 1;
-    e.n_real = S.n_real[slot]; e.n_ion = S.n_ion[slot];
-    e.n_masked = S.n_masked[slot]; e.n_band = S.n_band[slot]; e.n_over = S.n_over[slot];
-    e.trace = S.trace[slot];
+    e.n_real = live.n_real; e.n_ion = live.n_ion;
+    e.n_masked = live.n_masked; e.n_band = live.n_band; e.n_over = live.n_overflow;
+    e.trace = live.trace;
     e.Ex = R(0); e.Ey = R(0); e.Ez = R(0);
     if (kField == FIELD_SLAB) slab_field<R>(F, e.aval, e);
     uint32_t status = 0;
@@ -371,12 +368,10 @@ __global__ void __launch_bounds__(kBlock) k_generation(GasDev G, FieldDev F, Run
     } else {
       complete_ionisation<R, kBanded>(e, G, T, P, child);
       ionised = true;
-      S.x1[slot] = e.x; S.y1[slot] = e.y; S.z1[slot] = e.z; S.t1[slot] = e.t;
+      S.end[slot] = avm_end_record{e.x, e.y, e.z, e.t, 0.0, 0u, e.n_real, e.n_ion, 0u, e.n_masked,
+                                   e.n_band, e.n_over, e.trace};
       S.vx1[slot] = (double)e.vx; S.vy1[slot] = (double)e.vy; S.vz1[slot] = (double)e.vz;
       S.k1[slot] = e.k; S.band1[slot] = (uint32_t)e.band;
-      S.n_real[slot] = e.n_real; S.n_ion[slot] = e.n_ion;
-      S.n_masked[slot] = e.n_masked; S.n_band[slot] = e.n_band; S.n_over[slot] = e.n_over;
-      S.trace[slot] = e.trace;
     }
   }
   // stack processing for this wave: slots for the secondaries, then the
@@ -385,11 +380,9 @@ __global__ void __launch_bounds__(kBlock) k_generation(GasDev G, FieldDev F, Run
   const bool stored = ionised && cs < S.capacity;
   if (stored) {
     write_start<R>(S, cs, e, child);
-    S.x1[cs] = e.x; S.y1[cs] = e.y; S.z1[cs] = e.z; S.t1[cs] = e.t;
+    S.end[cs] = avm_end_record{e.x, e.y, e.z, e.t, 0.0, 0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
     S.vx1[cs] = (double)child.vx; S.vy1[cs] = (double)child.vy; S.vz1[cs] = (double)child.vz;
     S.k1[cs] = 0; S.band1[cs] = 0;
-    S.n_real[cs] = 0; S.n_ion[cs] = 0; S.n_null[cs] = 0; S.n_masked[cs] = 0;
-    S.n_band[cs] = 0; S.n_over[cs] = 0; S.status[cs] = 0; S.trace[cs] = 0;
   }
   const unsigned long long np = wave_alloc(&ctr->next, ionised);
   if (ionised) next[np] = slot;

@@ -101,10 +101,8 @@ extern "C" avm_status avm_run_noalloc(const avm_gas* gas, const avm_field* field
                                       const avm_noalloc_out* out) {
   if (!out) return set_error(AVM_E_ARG, "avm_run_noalloc: out is NULL");
   if (n_prim && !prim) return set_error(AVM_E_ARG, "avm_run_noalloc: primaries are NULL");
-  const void* arrays[] = {out->x0, out->y0, out->z0, out->t0, out->e0, out->x1, out->y1, out->z1,
-                          out->t1, out->e1, out->eid, out->parent, out->avalanche, out->status,
-                          out->n_real, out->n_ion, out->n_null, out->n_masked, out->n_band,
-                          out->n_overflow, out->trace, out->aval_counts, out->counts, out->flags};
+  const void* arrays[] = {out->x0, out->y0, out->z0, out->t0, out->e0, out->eid, out->parent,
+                          out->avalanche, out->end, out->aval_counts, out->counts, out->flags};
   for (const void* a : arrays)
     if (!a) return set_error(AVM_E_ARG, "avm_run_noalloc: an output array is NULL");
   NoallocSetup su{};
@@ -128,9 +126,7 @@ extern "C" avm_status avm_run_noalloc(const avm_gas* gas, const avm_field* field
     S.eid = out->eid; S.parent = out->parent; S.aval = out->avalanche;
     S.qready = reinterpret_cast<uint32_t*>(base + kOffQready);
     S.qslot = reinterpret_cast<uint32_t*>(base + kOffQslot);
-    S.x1 = out->x1; S.y1 = out->y1; S.z1 = out->z1; S.t1 = out->t1; S.e1 = out->e1;
-    S.status = out->status; S.n_real = out->n_real; S.n_ion = out->n_ion; S.n_null = out->n_null;
-    S.n_masked = out->n_masked; S.n_band = out->n_band; S.n_over = out->n_overflow; S.trace = out->trace;
+    S.end = out->end;
     S.stats = reinterpret_cast<AvalStats*>(out->aval_counts);
     S.tot = tot;
     S.capacity = opts->capacity;

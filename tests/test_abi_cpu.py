@@ -44,12 +44,50 @@ def test_library_exports_every_declared_symbol(A):
 
 
 def test_abi_version_and_sizes(A):
-    assert A.lib().avm_abi_version() == 2
+    assert A.lib().avm_abi_version() == 3
     assert A.ENDPOINT_DTYPE.itemsize == 136
+    assert A.END_RECORD_DTYPE.itemsize == 72
     assert W.PRIMARY_DTYPE.itemsize == 72
     assert C.sizeof(A._Counts) == 8 * 18 + 8
     assert C.sizeof(A._Opts) == 72
     assert C.sizeof(A._TuneResult) == 48
+    assert C.sizeof(A._EndpointArrays) == 9 * 8
+    assert C.sizeof(A._NoallocOut) == 12 * 8
+
+
+def test_record_layouts_match_the_header(A, tmp_path):
+    """The binding's record layouts against what a C compiler makes of
+    include/avm.h: sizes and field offsets."""
+    fields = {"avm_end_record": A.END_RECORD_DTYPE.names,
+              "avm_endpoint": [n if n != "aval" else "avalanche" for n in A.ENDPOINT_DTYPE.names
+                               if n != "_pad"]}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "avm.h"', "int main(void) {"]
+    for t, names in fields.items():
+        lines.append(f'  printf("{t} size %zu\\n", sizeof({t}));')
+        for n in names:
+            lines.append(f'  printf("{t} {n} %zu\\n", offsetof({t}, {n}));')
+    for t in ("avm_endpoint_arrays", "avm_noalloc_out"):
+        lines.append(f'  printf("{t} size %zu\\n", sizeof({t}));')
+    lines.append("  return 0;\n}")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    got = {}
+    for line in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n"):
+        if line:
+            t, n, v = line.split()
+            got[(t, n)] = int(v)
+    assert got[("avm_end_record", "size")] == A.END_RECORD_DTYPE.itemsize
+    for n in A.END_RECORD_DTYPE.names:
+        assert got[("avm_end_record", n)] == A.END_RECORD_DTYPE.fields[n][1], n
+    assert got[("avm_endpoint", "size")] == A.ENDPOINT_DTYPE.itemsize
+    for n in A.ENDPOINT_DTYPE.names:
+        if n != "_pad":
+            assert got[("avm_endpoint", "avalanche" if n == "aval" else n)] == A.ENDPOINT_DTYPE.fields[n][1], n
+    assert got[("avm_endpoint_arrays", "size")] == C.sizeof(A._EndpointArrays)
+    assert got[("avm_noalloc_out", "size")] == C.sizeof(A._NoallocOut)
 
 
 def test_argument_errors_without_a_device(A):
