@@ -37,6 +37,8 @@ struct Totals {
 #define AVM_GLB
 #endif
 struct Store {
+  // start arrays (vx0..vz0: only for primaries and queued electrons, which
+  // the claiming wave reads back)
   AVM_GLB double *x0, *y0, *z0, *t0, *vx0, *vy0, *vz0, *e0;
   AVM_GLB uint64_t *eid, *parent;
   AVM_GLB uint32_t* aval;

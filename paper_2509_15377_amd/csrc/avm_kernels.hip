@@ -214,7 +214,6 @@ AVM_FN void write_end(const Store& S, uint32_t s, const Elec<R>& e, const RunPar
 template <class R>
 AVM_FN void write_start(const Store& S, uint64_t s, const Elec<R>& parent, const Child<R>& c) {
   S.x0[s] = parent.x; S.y0[s] = parent.y; S.z0[s] = parent.z; S.t0[s] = parent.t;
-  S.vx0[s] = (double)c.vx; S.vy0[s] = (double)c.vy; S.vz0[s] = (double)c.vz;
   S.e0[s] = (double)c.e;
   S.eid[s] = c.eid;
   S.parent[s] = parent.eid;
@@ -574,8 +573,9 @@ __global__ void __launch_bounds__(kPBlock)
       // start record: the electron's output; queued ones are also read by
       // other waves, so those go out device-coherent
       if (local) {
+        // (the start velocity goes through LDS: only queued electrons need
+        // it in memory)
         S.x0[cs] = e.x; S.y0[cs] = e.y; S.z0[cs] = e.z; S.t0[cs] = e.t;
-        S.vx0[cs] = (double)child.vx; S.vy0[cs] = (double)child.vy; S.vz0[cs] = (double)child.vz;
         S.eid[cs] = child.eid;
         S.aval[cs] = e.aval;
         X.x[rank_c] = e.x; X.y[rank_c] = e.y; X.z[rank_c] = e.z; X.t[rank_c] = e.t;
