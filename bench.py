@@ -19,19 +19,51 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# Algorithmic VALU work per event, in lane operations (the minimum the
-# method performs per flight / real collision / ionisation / endpoint; see the
-# design notes for the derivation).  Peak: 256 CUs x 4 SIMD16 x 2.4 GHz x 16
-# lanes = 3.93e13 lane-ops/s (FP64 FMA counted as one op).
-OPS_PER_FLIGHT = 150
-OPS_PER_REAL = 220
-OPS_PER_ION = 280
+# Algorithmic VALU work per event: the minimum the method performs per
+# flight / real collision / ionisation, in issue slots of one 16-lane SIMD
+# (lane operations weighted by issue rate as measured on gfx950: FP64 add,
+# multiply and FMA, 32-bit integer multiplies and three-input bitwise
+# operations issue at one wave64 instruction per four cycles and count 1;
+# FP64 reciprocal and reciprocal square root issue at a quarter of that and
+# count 4).  Peak: 256 CUs x 4 SIMD16 x 2.4 GHz x 16 lanes = 3.93e13
+# lane-ops/s, the FP64 vector FMA rate.
+OPS_FLIGHT = {
+    "Philox block: 10 rounds of 2 mul_lo, 2 mul_hi, 2 three-input xor; counter": 62,
+    "two 53-bit uniforms": 8,
+    "logarithm of the flight uniform (one reciprocal)": 28,
+    "flight update: time, position, velocity": 11,
+    "energy at the flight end, band test": 6,
+    "decision: bin, two interpolations, comparisons": 10,
+    "flight index, counters, trace": 4,
+}
+OPS_REAL = {
+    "Philox block": 62,
+    "two uniforms": 8,
+    "screened scattering angle (one reciprocal)": 13,
+    "energy loss": 3,
+    "lab-frame cosine (one reciprocal square root)": 9,
+    "direction normalisation (one reciprocal square root)": 13,
+    "azimuth sin/cos": 30,
+    "sine of the polar angle (square root)": 9,
+    "rotation": 20,
+    "new speed (square root) and velocity": 11,
+    "channel search, band lookup, trace": 10,
+}
+OPS_ION = {
+    "two Philox blocks": 124,
+    "energy split (tangent, arc tangent)": 50,
+    "two directions: sin/cos, rotation, square roots": 116,
+}
 # the polar map and the magnetic field add, per flight: the map gather
-# (log of rho^2, azimuth, four-node bilinear weights and eight reads, the
-# rotation to Cartesian, ~95), the helical step (sin/cos of the gyration
-# phase and half of it, drift and gyration terms, ~105) and, with the band
-# majorant, the helical energy bound (three square roots, ~40)
-OPS_PER_FLIGHT_POLAR_B = 240
+# (logarithm of rho^2, azimuth, bilinear weights and reads, rotation to
+# Cartesian), the helical step (sin/cos of the half phase and the drift and
+# gyration terms) and, with the band majorant, the helical energy bound
+# (three square roots)
+OPS_FLIGHT_POLAR_B = {"map gather": 90, "helical step": 70, "helical energy bound": 40}
+OPS_PER_FLIGHT = sum(OPS_FLIGHT.values())
+OPS_PER_REAL = sum(OPS_REAL.values())
+OPS_PER_ION = sum(OPS_ION.values())
+OPS_PER_FLIGHT_POLAR_B = sum(OPS_FLIGHT_POLAR_B.values())
 PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 
 

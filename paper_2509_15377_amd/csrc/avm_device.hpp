@@ -5,7 +5,8 @@
 // the paper's Fig. 2 for one electron held in registers: check that it is
 // still inside the volume, take the local field and a random flight time,
 // decide whether a real collision ends the flight, and, for a real one,
-// which channel (an ionisation or an attachment changes the electron count).  The free flight is a null-collision flight (Skullerud, cited in
+// which channel (an ionisation or an attachment changes the electron
+// count).  The free flight is a null-collision flight (Skullerud, cited in
 // Sec. 1): exponential with the majorant rate, real with probability
 // nu(e)/majorant.  Both the plain (generation-synchronous) and the batched
 // (persistent) kernels call this same function, so for a given electron they
