@@ -639,11 +639,12 @@ template <class R>
 struct Child {
   R vx, vy, vz, e;
   uint64_t eid;
-  R pen;      // pending ionisation: energy at the collision
+  R pen;      // pending ionisation: energy at the collision; pending
+              // boundary exit: the flight's end time (STEP_EXIT)
   int32_t pc; // pending ionisation: channel
 };
 
-enum : int32_t { STEP_CONTINUE = 0, STEP_IONISED = 1, STEP_DONE = 2 };
+enum : int32_t { STEP_CONTINUE = 0, STEP_IONISED = 1, STEP_DONE = 2, STEP_EXIT = 3 };
 
 // Decision trace of an electron: a running 32-bit hash over its real
 // collisions, masked nulls and band cuts in flight order, so that two runs
@@ -1203,51 +1204,11 @@ AVM_FN int32_t flight_step(Elec<R>& e, const GasDev& G, const TV& T, const Field
     propagate<R, kMayHaveB>(F, e, ax, ay, az, Ex, Ey, Ez, tau_end, rx, ry, rz, ux, uy, uz);
     const double r2 = rx * rx + ry * ry;
     if (r2 <= F.a2 || r2 >= F.b2) {
-      // the time the boundary is crossed, between the flight start (inside)
-      // and its end (outside): a bracket [lo, hi] on the inside/outside
-      // predicate, shrunk at false-position points of
-      // g(s) = R^2 - rho(s)^2 (wire) or rho(s)^2 - R^2 (tube), negative
-      // inside, with the Illinois halving of the stale end's value, and at
-      // the midpoint when the interpolant leaves the bracket; it stops when
-      // the bracket is a few ulps wide (excursions that leave and re-enter
-      // within one flight are not detected)
-      const bool to_wire = r2 <= F.a2;
-      const double R2 = to_wire ? F.a2 : F.b2;
-      const double sg = to_wire ? -1.0 : 1.0;
-      const double q0 = e.x * e.x + e.y * e.y;
-      double lo = 0.0, hi = (double)tau_end;
-      double glo = sg * (q0 - R2), ghi = sg * (r2 - R2);
-      int last = 0;
-      // a few ulps of the flight time in the step's precision (the trial
-      // times are rounded to R for the flight formula)
-      const double eps = sizeof(R) == 4 ? 2.4e-7 : 4.5e-16;
-      for (int it = 0; it < 60 && hi - lo > eps * hi; ++it) {
-        double c = (lo * ghi - hi * glo) / (ghi - glo);
-        if (!(c > lo && c < hi)) c = 0.5 * (lo + hi);
-        double mx, my, mz;
-        R wx_, wy_, wz_;
-        propagate<R, kMayHaveB>(F, e, ax, ay, az, Ex, Ey, Ez, (R)c, mx, my, mz, wx_, wy_, wz_);
-        const double m2 = mx * mx + my * my;
-        const double gc = sg * (m2 - R2);
-        if (m2 <= F.a2 || m2 >= F.b2) {
-          hi = c;
-          ghi = gc > 0.0 ? gc : 0.0;
-          if (last < 0) glo *= 0.5;
-          last = -1;
-        } else {
-          lo = c;
-          glo = gc < 0.0 ? gc : -0.0;
-          if (last > 0) ghi *= 0.5;
-          last = 1;
-        }
-      }
-      s_exit = hi;
-      propagate<R, kMayHaveB>(F, e, ax, ay, az, Ex, Ey, Ez, (R)s_exit, rx, ry, rz, ux, uy, uz);
-      const double q2 = rx * rx + ry * ry;
-      side = q2 <= F.a2 ? ST_WIRE : ST_TUBE;
-      const double sc = (side == ST_WIRE ? F.a : F.b) / sqrt(q2);
-      rx = rx * sc;
-      ry = ry * sc;
+      // the flight ends on the wire or beyond the tube: the electron stops
+      // here, unchanged, and the caller finds the crossing with
+      // finish_exit() after the pass, for all such lanes of the wave at once
+      child.pen = tau_end;
+      return STEP_EXIT;
     }
   }
   if (kSignal) signal_flight<R, kMayHaveB, kField>(*Q, F, e, ax, ay, az, Ex, Ey, Ez,
@@ -1343,6 +1304,75 @@ AVM_FN int32_t flight_step(Elec<R>& e, const GasDev& G, const TV& T, const Field
   if (st == 0 && ret == STEP_CONTINUE) e.k += 1;
   status = st;
   return st ? STEP_DONE : ret;
+}
+
+// The flight of a STEP_EXIT (polar-map geometry): the electron stands at
+// the flight start; its flight of duration tau_end (child.pen) ends on the
+// wire or beyond the tube.  Finds the time the boundary is crossed,
+// between the flight start (inside) and its end (outside): a bracket
+// [lo, hi] on the inside/outside predicate, shrunk at false-position points
+// of g(s) = R^2 - rho(s)^2 (wire) or rho(s)^2 - R^2 (tube), negative
+// inside, with the Illinois halving of the stale end's value, and at the
+// midpoint when the interpolant leaves the bracket; it stops when the
+// bracket is a few ulps wide (excursions that leave and re-enter within one
+// flight are not detected).  Moves the electron to the crossing (on the
+// boundary surface) and returns its status, ST_WIRE or ST_TUBE.  The lanes
+// of a wave that ended a pass this way search together.
+template <class R, bool kBanded, bool kSignal = false>
+AVM_FN uint32_t finish_exit(Elec<R>& e, const FieldDev& F, const RunParams& P, R tau_end,
+                            const SignalDev* Q = nullptr) {
+  constexpr bool kMayHaveB = true;  // polar-map geometry
+  R Ex = e.Ex, Ey = e.Ey, Ez = e.Ez;
+  polar_field<R>(F, e.x, e.y, Ex, Ey);
+  Ez = R(0);
+  const R ka = Sel<R>::k_a(P);
+  const R ax = -ka * Ex, ay = -ka * Ey, az = -ka * Ez;
+  double rx, ry, rz;
+  R ux, uy, uz;
+  propagate<R, kMayHaveB>(F, e, ax, ay, az, Ex, Ey, Ez, tau_end, rx, ry, rz, ux, uy, uz);
+  const double r2 = rx * rx + ry * ry;
+  const bool to_wire = r2 <= F.a2;
+  const double R2 = to_wire ? F.a2 : F.b2;
+  const double sg = to_wire ? -1.0 : 1.0;
+  const double q0 = e.x * e.x + e.y * e.y;
+  double lo = 0.0, hi = (double)tau_end;
+  double glo = sg * (q0 - R2), ghi = sg * (r2 - R2);
+  int last = 0;
+  // a few ulps of the flight time in the step's precision (the trial
+  // times are rounded to R for the flight formula)
+  const double eps = sizeof(R) == 4 ? 2.4e-7 : 4.5e-16;
+  for (int it = 0; it < 60 && hi - lo > eps * hi; ++it) {
+    double c = (lo * ghi - hi * glo) / (ghi - glo);
+    if (!(c > lo && c < hi)) c = 0.5 * (lo + hi);
+    double mx, my, mz;
+    R wx_, wy_, wz_;
+    propagate<R, kMayHaveB>(F, e, ax, ay, az, Ex, Ey, Ez, (R)c, mx, my, mz, wx_, wy_, wz_);
+    const double m2 = mx * mx + my * my;
+    const double gc = sg * (m2 - R2);
+    if (m2 <= F.a2 || m2 >= F.b2) {
+      hi = c;
+      ghi = gc > 0.0 ? gc : 0.0;
+      if (last < 0) glo *= 0.5;
+      last = -1;
+    } else {
+      lo = c;
+      glo = gc < 0.0 ? gc : -0.0;
+      if (last > 0) ghi *= 0.5;
+      last = 1;
+    }
+  }
+  const double s_exit = hi;
+  propagate<R, kMayHaveB>(F, e, ax, ay, az, Ex, Ey, Ez, (R)s_exit, rx, ry, rz, ux, uy, uz);
+  const double q2 = rx * rx + ry * ry;
+  const uint32_t side = q2 <= F.a2 ? ST_WIRE : ST_TUBE;
+  const double sc = (side == ST_WIRE ? F.a : F.b) / sqrt(q2);
+  rx = rx * sc;
+  ry = ry * sc;
+  if (kSignal) signal_flight<R, kMayHaveB, FIELD_POLAR>(*Q, F, e, ax, ay, az, Ex, Ey, Ez, e.t + s_exit);
+  e.x = rx; e.y = ry; e.z = rz;
+  e.vx = ux; e.vy = uy; e.vz = uz;
+  e.t = e.t + s_exit;
+  return side;
 }
 
 // Finishes an ionisation (or a Penning transfer) decided by flight_step

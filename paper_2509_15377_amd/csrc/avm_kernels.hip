@@ -361,6 +361,12 @@ __global__ void __launch_bounds__(kBlock) k_generation(GasDev G, FieldDev F, Run
         r = STEP_DONE;
       }
     } while (r == STEP_CONTINUE);
+    if (kField == FIELD_POLAR && r == STEP_EXIT) {
+      // the crossing of the flight that left the volume (the lanes of the
+      // wave that got here search together)
+      status = finish_exit<R, kBanded>(e, F, P, child.pen);
+      r = STEP_DONE;
+    }
     if (r == STEP_DONE) {
       write_end(S, slot, e, P, status);
       term = status;
@@ -529,7 +535,8 @@ __global__ void __launch_bounds__(kPBlock)
     }
     // ---- transport pass
     uint32_t term = 0;  // status of this lane's electron if it terminated in this pass
-    for (int f = 0; f < flights_per_pass && has && !cp; ++f) {
+    bool xp = false;    // the electron's last flight left the volume (polar map)
+    for (int f = 0; f < flights_per_pass && has && !cp && !xp; ++f) {
       uint32_t status = 0;
       const int32_t r = flight_step<R, kBanded, kField, kSignal>(e, G, T, F, P, child, status, &Q);
       if (r == STEP_IONISED) {
@@ -537,7 +544,14 @@ __global__ void __launch_bounds__(kPBlock)
       } else if (r == STEP_DONE) {
         has = false;
         term = status;
+      } else if (kField == FIELD_POLAR && r == STEP_EXIT) {
+        xp = true;
       }
+    }
+    // ---- boundary crossings of this pass, found together
+    if (kField == FIELD_POLAR && xp) {
+      term = finish_exit<R, kBanded, kSignal>(e, F, P, child.pen, &Q);
+      has = false;
     }
     // ---- endpoints of this pass, written together (the state of a
     // terminated electron stays in place until the exchange)
