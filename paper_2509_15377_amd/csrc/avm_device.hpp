@@ -999,11 +999,13 @@ AVM_FN void scatter_to(Elec<R>& e, const RunParams& P, R cos_t, R uB, R e_new) {
 // the channel: the smallest c with r_sel < interpolated cumulative rate c
 // (channel 0 first -- the elastic channel dominates -- then a binary search
 // over the rest; interpolated cumulative rates are non-decreasing in c).
-// `margin` returns the smallest relative distance of r_sel to a rate it was
-// compared with, or of en to the window edge it was compared with; `over`
-// tells whether en lies above the table.
+// `close` tells whether r_sel lies within a relative 2^-18 of a rate it was
+// compared with, or en within a relative 2^-18 of the window edge it was
+// compared with (tested by multiplying with the power of two, which is
+// exact, instead of dividing); `over` tells whether en lies above the table.
+constexpr double kCloseRel = 3.814697265625e-6;  // 2^-18
 template <class R, class TV>
-AVM_FN int decide(const GasDev& G, const TV& T, R en, R r_sel, R& margin, bool& over) {
+AVM_FN int decide(const GasDev& G, const TV& T, R en, R r_sel, bool& close, bool& over) {
   using Mr = M<R>;
   const R x = en * Sel<R>::scale(G);
   int32_t kb;
@@ -1031,7 +1033,7 @@ AVM_FN int decide(const GasDev& G, const TV& T, R en, R r_sel, R& margin, bool& 
   }
   R mg = Mr::abs_(r_sel - nu_tot);
   if (r_sel >= nu_tot) {
-    margin = mg / r_sel;
+    close = mg <= R(kCloseRel) * r_sel;
     return -1;
   }
   int c = 0;
@@ -1081,15 +1083,15 @@ AVM_FN int decide(const GasDev& G, const TV& T, R en, R r_sel, R& margin, bool& 
     }
     c = lo;
   }
-  margin = mg / r_sel;
+  close = mg <= R(kCloseRel) * r_sel;
   const ChanP<R> cw = chan(G, T, c);
   const double e_lo = cw.e_lo;
   const double e_hi = cw.e_hi;
   const double ed = (double)en;
   if (sizeof(R) == 4) {
     const double dl = fabs(ed - e_lo), dh = fabs(ed - e_hi);
-    const double d = (dl < dh ? dl : dh) / (ed > 1e-30 ? ed : 1e-30);
-    margin = (R)d < margin ? (R)d : margin;
+    const double d = dl < dh ? dl : dh;
+    close = close || d <= kCloseRel * (ed > 1e-30 ? ed : 1e-30);
   }
   if (ed < e_lo || ed >= e_hi) return -2 - c;
   return c;
@@ -1233,15 +1235,14 @@ AVM_FN int32_t flight_step(Elec<R>& e, const GasDev& G, const TV& T, const Field
       if (!(en < Mr::inf())) {
         st = ST_ERROR;
       } else {
-        R margin;
-        bool over;
-        int c = decide<R>(G, T, en, u2 * gam, margin, over);
-        if (kMixed && margin <= R(3.814697265625e-6)) {
+        bool close, over;
+        int c = decide<R>(G, T, en, u2 * gam, close, over);
+        if (kMixed && close) {
           // too close to call in FP32: decide again in FP64 for this state
           const double vx = (double)e.vx, vy = (double)e.vy, vz = (double)e.vz;
           const double en64 = dot3<double>(vx, vy, vz, vx, vy, vz) * P.inv_2ka;
-          double m64;
-          c = decide<double>(G, global_view<double>(G), en64, u53(w.w2, w.w3) * (double)gam, m64, over);
+          bool close64;
+          c = decide<double>(G, global_view<double>(G), en64, u53(w.w2, w.w3) * (double)gam, close64, over);
         }
         if (over) e.n_over += 1;
         R e_band = en;  // energy whose band the next flight starts in
