@@ -159,6 +159,53 @@ def test_wire_crossed_map_per_trajectory(A, oracle_mod, majorant):
     assert tot["n_status"][7] > 0
 
 
+def _near_boundaries(wl):
+    """Sixteen primaries of the wire chamber whose electrons reach a
+    boundary within a few thousand flights: eight at rest 40 um from the
+    axis (15 um outside the wire, in the multiplying field) and eight of
+    2 eV 1 um inside the tube, moving radially outward."""
+    p = W.primaries_at_rest(16)
+    phi = np.linspace(0.0, 2.0 * math.pi, 8, endpoint=False) + 0.1
+    rho = np.r_[np.full(8, 40e-4), np.full(8, 0.4999)]
+    p["x"] = rho * np.cos(np.r_[phi, phi])
+    p["y"] = rho * np.sin(np.r_[phi, phi])
+    p["e"][8:] = 2.0
+    p["dx"][8:] = np.cos(phi)
+    p["dy"][8:] = np.sin(phi)
+    p["dz"][8:] = 0.0
+    return p
+
+
+@pytest.mark.parametrize("majorant", ["global", "banded"])
+def test_wire_and_tube_crossings_per_trajectory(A, oracle_mod, majorant):
+    """The boundary crossing of the polar geometry (the flight that ends on
+    the wire or beyond the tube, cut where it crosses), per trajectory
+    against the oracle's sixty halvings, for electrons that reach the wire
+    and the tube within 4000 flights, in the batched and the plain mode
+    (which must agree bit for bit), global majorant and helical band bound."""
+    wl = W.wire()
+    prim = _near_boundaries(wl)
+    if majorant == "global":
+        ref = oracle_mod.run(wl.gas, wl.field, prim, wl.seed, k_max=4000)
+        kw = dict(primaries=prim, n_aval=16, capacity=200_000, k_max=4000)
+    else:
+        og = oracle_mod.Gas(wl.gas, band_bins=100)
+        ref = oracle_mod.run(og, wl.field, prim, wl.seed, banded=True, k_max=4000)
+        kw = dict(primaries=prim, n_aval=16, band_bins=100, majorant=A.BANDED, capacity=200_000,
+                  k_max=4000)
+    ep, tot, _ = A.run(wl, mode=A.BATCHED, **kw)
+    ep_plain, tot_plain, _ = A.run(wl, mode=A.PLAIN, **kw)
+    assert ep.tobytes() == ep_plain.tobytes()
+    rep = CMP.assert_parity(ep, ref, max_flips=0)
+    print("wire and tube crossings", majorant, rep)
+    st = tot["n_status"]
+    assert st[4] >= 20 and st[5] >= 4, st  # on the wire, beyond the tube
+    on_wire = ep["status"] == 4
+    assert np.allclose(np.hypot(ep["x1"][on_wire], ep["y1"][on_wire]), 25e-4, rtol=1e-12)
+    on_tube = ep["status"] == 5
+    assert np.allclose(np.hypot(ep["x1"][on_tube], ep["y1"][on_tube]), 0.5, rtol=1e-12)
+
+
 def test_full_argon_bench_configuration_sampled(A, oracle_mod):
     """The benchmark's launch configuration (1000 avalanches, batched,
     banded with lookahead 1, FP64, graph replay) checked on every 50th
