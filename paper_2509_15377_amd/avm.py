@@ -70,6 +70,14 @@ class _Counts(C.Structure):
                 ("n_requested", C.c_uint64), ("truncated", C.c_uint32), ("_pad", C.c_uint32)]
 
 
+# numpy view of an array of avm_counts records
+COUNTS_DTYPE = np.dtype([(n, "<u8") for n in ("n_endpoints", "n_ion", "n_att", "n_real", "n_null",
+                                               "n_masked", "n_band", "n_overflow")]
+                        + [("n_status", "<u8", (9,)), ("n_requested", "<u8"), ("truncated", "<u4"),
+                           ("_pad", "<u4")])
+assert COUNTS_DTYPE.itemsize == C.sizeof(_Counts)
+
+
 class _TuneResult(C.Structure):
     _fields_ = [("flights_per_pass", C.c_int32), ("waves_per_cu", C.c_int32),
                 ("band_bins", C.c_int32), ("trials", C.c_int32), ("from_cache", C.c_int32),
@@ -132,7 +140,7 @@ _SIGS = {
     "avm_run_execute": ([_VP], C.c_int),
     "avm_run_sync": ([_VP], C.c_int),
     "avm_run_counts": ([_VP, C.POINTER(_Counts)], C.c_int),
-    "avm_run_avalanche_counts": ([_VP, C.c_uint32, C.c_uint32, C.POINTER(_Counts)], C.c_int),
+    "avm_run_avalanche_counts": ([_VP, C.c_uint32, C.c_uint32, _VP], C.c_int),
     "avm_run_num_endpoints": ([_VP, C.POINTER(C.c_uint64)], C.c_int),
     "avm_run_endpoints": ([_VP, C.c_uint64, C.c_uint64, _VP], C.c_int),
     "avm_run_endpoint_arrays": ([_VP, C.POINTER(_EndpointArrays)], C.c_int),
@@ -373,10 +381,11 @@ class Run:
         return _counts_dict(c)
 
     def avalanche_counts(self):
-        arr = (_Counts * self.n_aval)()
-        _check(lib().avm_run_avalanche_counts(self.h, 0, self.n_aval, arr))
+        a = np.zeros(self.n_aval, dtype=COUNTS_DTYPE)
+        if self.n_aval:
+            _check(lib().avm_run_avalanche_counts(self.h, 0, self.n_aval, C.c_void_p(a.ctypes.data)))
         keys = ("n_endpoints", "n_ion", "n_att", "n_real", "n_null", "n_masked", "n_band", "n_overflow")
-        return {k: np.array([getattr(a, k) for a in arr], dtype=np.int64) for k in keys}
+        return {k: a[k].astype(np.int64) for k in keys}
 
     def num_endpoints(self):
         n = C.c_uint64()

@@ -58,7 +58,8 @@ def test_abi_version_and_sizes(A):
 def test_record_layouts_match_the_header(A, tmp_path):
     """The binding's record layouts against what a C compiler makes of
     include/avm.h: sizes and field offsets."""
-    fields = {"avm_end_record": A.END_RECORD_DTYPE.names,
+    fields = {"avm_counts": [n for n in A.COUNTS_DTYPE.names if n != "_pad"],
+              "avm_end_record": A.END_RECORD_DTYPE.names,
               "avm_endpoint": [n if n != "aval" else "avalanche" for n in A.ENDPOINT_DTYPE.names
                                if n != "_pad"]}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "avm.h"', "int main(void) {"]
@@ -79,6 +80,10 @@ def test_record_layouts_match_the_header(A, tmp_path):
         if line:
             t, n, v = line.split()
             got[(t, n)] = int(v)
+    assert got[("avm_counts", "size")] == A.COUNTS_DTYPE.itemsize
+    for n in A.COUNTS_DTYPE.names:
+        if n != "_pad":
+            assert got[("avm_counts", n)] == A.COUNTS_DTYPE.fields[n][1], n
     assert got[("avm_end_record", "size")] == A.END_RECORD_DTYPE.itemsize
     for n in A.END_RECORD_DTYPE.names:
         assert got[("avm_end_record", n)] == A.END_RECORD_DTYPE.fields[n][1], n
