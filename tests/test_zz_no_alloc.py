@@ -69,6 +69,33 @@ def test_noalloc_matches_run_twice(A):
     _same(ref2, got2)
 
 
+def test_noalloc_polar_map_crossings(A):
+    """The polar-map kernel through avm_run_noalloc: wire-chamber electrons
+    that end on the wire and beyond the tube within 4000 flights (the
+    boundary crossings found after the pass), against the allocating entry
+    points, with the helical band bound."""
+    import math
+    wl = W.wire()
+    g = A.Gas(wl.gas, band_bins=100)
+    f = A.Field(wl.field)
+    p = W.primaries_at_rest(16)
+    phi = np.linspace(0.0, 2.0 * math.pi, 8, endpoint=False) + 0.1
+    rho = np.r_[np.full(8, 40e-4), np.full(8, 0.4999)]
+    p["x"] = rho * np.cos(np.r_[phi, phi])
+    p["y"] = rho * np.sin(np.r_[phi, phi])
+    p["e"][8:] = 2.0
+    p["dx"][8:] = np.cos(phi)
+    p["dy"][8:] = np.sin(phi)
+    p["dz"][8:] = 0.0
+    kw = dict(majorant=A.BANDED, k_max=4000)
+    print("noalloc: wire chamber near the boundaries, FP64 banded", flush=True)
+    ref = _reference(A, g, f, p, 16, wl.seed, 200_000, **kw)
+    got = _noalloc(A, g, f, p, 16, wl.seed, 200_000, **kw)
+    _same(ref, got)
+    st = ref[1]["n_status"]
+    assert st[4] > 0 and st[5] > 0
+
+
 def test_noalloc_truncation_and_errors(A):
     import torch
     wl = W.toy(40)
