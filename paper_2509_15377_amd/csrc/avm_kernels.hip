@@ -286,6 +286,85 @@ AVM_FN void tally_ends(bool ended, uint32_t status, const Elec<R>& e, const Stor
   }
 }
 
+// Per-wave statistics accumulator of the persistent kernel, in LDS: the
+// counters (as AvalStats) of the electrons the wave terminated for one
+// avalanche, `tag`.  They go to the avalanche's counters in device memory
+// (and to the block's totals) only when the wave ends electrons of another
+// avalanche while holding none of this one, or when the wave leaves.
+struct WaveAcc {
+  unsigned long long c[8];
+  uint32_t tag, _pad;
+};
+constexpr uint32_t kNoTag = 0xFFFFFFFFu;  // avalanche ids are below n_aval <= 2^32 - 1
+
+// Lanes 0..7 add counter `lane` of the accumulator to its avalanche and to
+// the block's totals, and clear it (every lane of the wave calls it).
+AVM_FN void acc_flush(AVM_LDS WaveAcc* W, const Store& S, AVM_LDS unsigned long long* blk) {
+  const uint32_t tag = __builtin_amdgcn_readfirstlane(W->tag);
+  if (tag == kNoTag) return;
+  const uint32_t lane = __lane_id();
+  if (lane < 8) {
+    const unsigned long long v = W->c[lane];
+    if (v) {
+      __hip_atomic_fetch_add(&S.stats[tag].c[lane], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(blk + lane, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+    W->c[lane] = 0ull;
+  }
+}
+
+// The persistent kernel's form of tally_ends: the ended lanes of the
+// accumulator's avalanche add their counters to it in LDS (one LDS atomic
+// per counter and lane); when no ended lane belongs to it, the accumulator
+// is flushed and taken over by the avalanche of the first ended lane; lanes
+// of any further avalanche add to device memory directly.  The status
+// histogram goes to the block's totals.
+template <class R>
+AVM_FN void tally_ends_acc(bool ended, uint32_t status, const Elec<R>& e, const Store& S,
+                           AVM_LDS WaveAcc* W, AVM_LDS unsigned long long* blk) {
+  const uint64_t m = __ballot(ended);
+  if (!m) return;
+  uint32_t tag = __builtin_amdgcn_readfirstlane(W->tag);
+  if (__ballot(ended && e.aval == tag) == 0) {
+    acc_flush(W, S, blk);
+    tag = __builtin_amdgcn_readlane(e.aval, __builtin_ctzll(m));
+    if (__lane_id() == 0) W->tag = tag;
+  }
+  // counter j of this lane's electron (formed where it is used, one at a time)
+  const auto val = [&](int j) -> uint32_t {
+    switch (j) {
+      case 0: return 1u;
+      case 1: return e.n_ion;
+      case 2: return status == ST_ATTACHED ? 1u : 0u;
+      case 3: return e.n_real;
+      case 4: return null_count(e, status);
+      case 5: return e.n_masked;
+      case 6: return e.n_band;
+      default: return e.n_over;
+    }
+  };
+  if (ended && e.aval == tag) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const uint32_t x = val(j);
+      if (x) __hip_atomic_fetch_add(&W->c[j], (unsigned long long)x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+    }
+  } else if (ended) {
+    AVM_GLB unsigned long long* dst = S.stats[e.aval].c;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const uint32_t x = val(j);
+      if (x) {
+        __hip_atomic_fetch_add(dst + j, (unsigned long long)x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(blk + j, (unsigned long long)x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      }
+    }
+  }
+  if (ended)
+    __hip_atomic_fetch_add(blk + 8 + (status < 9 ? status : 8), 1ull, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 // A block's totals go to the run's totals (after the block's last tally).
 AVM_FN void flush_tally(const AVM_LDS unsigned long long* blk, AVM_GLB Totals* tot) {
   const int i = threadIdx.x;
@@ -496,7 +575,10 @@ __global__ void __launch_bounds__(kPBlock)
   __shared__ R s_bg[kLdsBands], s_bi[kLdsBands], s_be[kLdsBands];
   __shared__ ChanP<R> s_ch[kLdsChannels];
   __shared__ unsigned long long s_tally[kTally];
+  __shared__ WaveAcc wacc_all[kPBlock / 64];
   if (threadIdx.x < kTally) s_tally[threadIdx.x] = 0;
+  if ((threadIdx.x & 63u) < 8u) wacc_all[threadIdx.x >> 6].c[threadIdx.x & 63u] = 0ull;
+  if ((threadIdx.x & 63u) == 0u) wacc_all[threadIdx.x >> 6].tag = kNoTag;
   const TabView<R> Tg = global_view<R>(G);
   const int n_lo = G.n_bins + 1 < kLdsNodes ? G.n_bins + 1 : kLdsNodes;
   for (int k = threadIdx.x; k < n_lo; k += kPBlock) {
@@ -559,7 +641,8 @@ __global__ void __launch_bounds__(kPBlock)
       if (kSignal) signal_end<R, kField>(Q, e);
       write_end<R>(pinned(Sg), slot, e, P, term);
     }
-    tally_ends<R>(term != 0, term, e, pinned(Sg), (AVM_LDS unsigned long long*)s_tally);
+    tally_ends_acc<R>(term != 0, term, e, pinned(Sg), (AVM_LDS WaveAcc*)&wacc_all[threadIdx.x >> 6],
+                      (AVM_LDS unsigned long long*)s_tally);
     // ---- ionisations of this pass, finished together
     // (the secondary is born where its parent stands: e.x, e.y, e.z, e.t)
     if (cp) complete_ionisation<R, kBanded>(e, G, T, P, child);
@@ -699,7 +782,9 @@ __global__ void __launch_bounds__(kPBlock)
       idle_naps = 0;
     }
   }
-  // every wave of the block has left the loop: the block's totals go out
+  // the wave's accumulated statistics go out; once every wave of the block
+  // has left the loop, the block's totals
+  acc_flush((AVM_LDS WaveAcc*)&wacc_all[threadIdx.x >> 6], pinned(Sg), (AVM_LDS unsigned long long*)s_tally);
   __syncthreads();
   flush_tally((const AVM_LDS unsigned long long*)s_tally, pinned(Sg).tot);
 }
