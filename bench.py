@@ -22,13 +22,14 @@ if ROOT not in sys.path:
 # Algorithmic VALU work per event: the minimum the method performs per
 # flight / real collision / ionisation, in issue slots of one 16-lane SIMD
 # (lane operations weighted by issue rate as measured on gfx950: FP64 add,
-# multiply and FMA, 32-bit integer multiplies and three-input bitwise
-# operations issue at one wave64 instruction per four cycles and count 1;
+# multiply and FMA, 32-bit integer multiplies (v_mad_u64_u32 gives both
+# halves of a 32 x 32-bit product) and three-input bitwise operations issue
+# at one wave64 instruction per four cycles and count 1;
 # FP64 reciprocal and reciprocal square root issue at a quarter of that and
 # count 4).  Peak: 256 CUs x 4 SIMD16 x 2.4 GHz x 16 lanes = 3.93e13
 # lane-ops/s, the FP64 vector FMA rate.
 OPS_FLIGHT = {
-    "Philox block: 10 rounds of 2 mul_lo, 2 mul_hi, 2 three-input xor; counter": 62,
+    "Philox block: 10 rounds of 2 mad_u64_u32 (both halves of a product), 2 three-input xor; counter": 42,
     "two 53-bit uniforms": 8,
     "logarithm of the flight uniform (one reciprocal)": 28,
     "flight update: time, position, velocity": 11,
@@ -37,7 +38,7 @@ OPS_FLIGHT = {
     "flight index, counters, trace": 4,
 }
 OPS_REAL = {
-    "Philox block": 62,
+    "Philox block": 42,
     "two uniforms": 8,
     "screened scattering angle (one reciprocal)": 13,
     "energy loss": 3,
@@ -50,7 +51,7 @@ OPS_REAL = {
     "channel search, band lookup, trace": 10,
 }
 OPS_ION = {
-    "two Philox blocks": 124,
+    "two Philox blocks": 84,
     "energy split (tangent, arc tangent)": 50,
     "two directions: sin/cos, rotation, square roots": 116,
 }
