@@ -478,7 +478,11 @@ def main():
                      "unit": "lane-ops/s", "frac": achieved / PEAK_LANE_OPS,
                      "traffic": measured_traffic() if args.workload == "argon" else None,
                      "kernel": "k_persistent<banded,%s>" % ("polar" if args.workload == "wire" else "slab"), "kernel_ms": k_ms,
-                     "ops_per_launch": ops},
+                     "ops_per_launch": ops,
+                     "ops_model": "minimal VALU issue slots, weighted by measured issue rate: per flight %d, "
+                                  "per real collision +%d, per ionisation +%d%s" % (
+                                      OPS_PER_FLIGHT, OPS_PER_REAL, OPS_PER_ION,
+                                      ", per polar/B flight +%d" % OPS_PER_FLIGHT_POLAR_B if args.workload == "wire" else "")},
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
