@@ -443,6 +443,12 @@ template <> struct M<double> {
   AVM_FN static void sincospi_(double x, double* s, double* c) { sincospi_pos(x, s, c); }
   AVM_FN static double abs_(double x) { return fabs(x); }
   AVM_FN static double inf() { return __builtin_inf(); }
+  // the sampling and scattering forms (flight-time logarithm, scattering
+  // and emission angles, speeds): the accurate ones in FP64
+  AVM_FN static double log_s(double x) { return log_pos(x); }
+  AVM_FN static double sqrt_s(double x) { return sqrt_nn(x); }
+  AVM_FN static double rsqrt_s(double x) { return rsqrt_pos(x); }
+  AVM_FN static void sincos2pi_s(double u, double* s, double* c) { sincospi_pos(u + u, s, c); }
 };
 template <> struct M<float> {
   AVM_FN static float uni(uint32_t hi, uint32_t) { return u24(hi); }
@@ -456,6 +462,26 @@ template <> struct M<float> {
   AVM_FN static void sincospi_(float x, float* s, float* c) { sincospif(x, s, c); }
   AVM_FN static float abs_(float x) { return fabsf(x); }
   AVM_FN static float inf() { return __builtin_inff(); }
+  // the sampling and scattering forms in FP32-mixed: the hardware
+  // approximations (log2, square root and reciprocal square root to about
+  // 1 ulp; sin and cos of 2 pi u with u in turns), whose errors enter only
+  // sampled flight times, angles and speeds; the library forms above stay
+  // where a bound depends on the result (band crossings, helical steps)
+#ifdef AVM_HOST_DEBUG
+  AVM_FN static float log_s(float x) { return logf(x); }
+  AVM_FN static float sqrt_s(float x) { return sqrtf(x); }
+  AVM_FN static float rsqrt_s(float x) { return 1.0f / sqrtf(x); }
+  AVM_FN static void sincos2pi_s(float u, float* s, float* c) { sincospif(u + u, s, c); }
+#else
+  AVM_FN static float log_s(float x) { return __builtin_amdgcn_logf(x) * 0.693147180559945309f; }
+  AVM_FN static float sqrt_s(float x) { return __builtin_amdgcn_sqrtf(x); }
+  AVM_FN static float rsqrt_s(float x) { return __builtin_amdgcn_rsqf(x); }
+  AVM_FN static void sincos2pi_s(float u, float* s, float* c) {
+    const float t = u - floorf(u);  // [0, 1) turns
+    *s = __builtin_amdgcn_sinf(t);
+    *c = __builtin_amdgcn_cosf(t);
+  }
+#endif
 };
 
 template <class R>
@@ -475,13 +501,13 @@ AVM_FN R lerp(R a, R b, R g1, R f) { return M<R>::fma(f, b, g1 * a); }
 template <class R>
 AVM_FN void turn(R dx, R dy, R dz, R cos_t, R u_phi, R& ox, R& oy, R& oz) {
   const R st2 = M<R>::fma(-cos_t, cos_t, R(1));
-  const R sin_t = st2 > R(0) ? M<R>::sqrt_(st2) : R(0);
+  const R sin_t = st2 > R(0) ? M<R>::sqrt_s(st2) : R(0);
   R sp, cp;
-  M<R>::sincospi_(R(2) * u_phi, &sp, &cp);
+  M<R>::sincos2pi_s(u_phi, &sp, &cp);
   const R q = M<R>::fma(dx, dx, dy * dy);
   const R tiny = sizeof(R) == 8 ? R(1e-24) : R(1e-12);
   if (q > tiny) {
-    const R inv_s = M<R>::rsqrt_(q);
+    const R inv_s = M<R>::rsqrt_s(q);
     const R s = q * inv_s;
     const R a = sin_t * inv_s;
     ox = M<R>::fma(dx, cos_t, a * M<R>::fma(dx * dz, cp, -dy * sp));
@@ -981,14 +1007,14 @@ AVM_FN void scatter_to(Elec<R>& e, const RunParams& P, R cos_t, R uB, R e_new) {
   const R v2 = dot3<R>(e.vx, e.vy, e.vz, e.vx, e.vy, e.vz);
   R dx = R(0), dy = R(0), dz = R(1);
   if (v2 > R(0)) {
-    const R inv = M<R>::rsqrt_(v2);
+    const R inv = M<R>::rsqrt_s(v2);
     dx = e.vx * inv;
     dy = e.vy * inv;
     dz = e.vz * inv;
   }
   R ox, oy, oz;
   turn<R>(dx, dy, dz, cos_t, uB, ox, oy, oz);
-  const R sp1 = M<R>::sqrt_(Sel<R>::two_ka(P) * e_new);
+  const R sp1 = M<R>::sqrt_s(Sel<R>::two_ka(P) * e_new);
   e.vx = sp1 * ox;
   e.vy = sp1 * oy;
   e.vz = sp1 * oz;
@@ -1137,7 +1163,7 @@ AVM_FN int32_t flight_step(Elec<R>& e, const GasDev& G, const TV& T, const Field
   const int32_t band0 = e.band;
   const R gam0 = kBanded ? band_gamma(G, T, band0) : Sel<R>::gamma(G);
   const R inv0 = kBanded ? band_inv(G, T, band0) : Sel<R>::inv_gamma(G);
-  const R nlog = -Mr::log_(u1);
+  const R nlog = -Mr::log_s(u1);
   if (kBanded && P.look > 0.0 && e.band < G.n_bands - 1) {
     // lookahead: raise the band to the band of the energy after `look` mean
     // free times of the current band (the flight energy, or its helical
@@ -1272,7 +1298,7 @@ AVM_FN int32_t flight_step(Elec<R>& e, const GasDev& G, const TV& T, const Field
               const R cchi = ch.angular ? R(1) - R(2) * uA / Mr::fma(R(1) - uA, en * ch.inv_screen8, R(1))
                                         : R(1) - R(2) * uA;
               e_new = en * (R(1) - ch.el_loss * (R(1) - cchi));
-              cos_t = (ch.mu + cchi) * Mr::rsqrt_(Mr::fma(ch.two_mu, cchi, ch.mu2p1));
+              cos_t = (ch.mu + cchi) * Mr::rsqrt_s(Mr::fma(ch.two_mu, cchi, ch.mu2p1));
             } else {  // excitation
               if (ch.pen_prob > R(0)) {
                 // Penning transfer, decided by the first uniform of block 2:
@@ -1406,10 +1432,10 @@ AVM_FN void complete_ionisation(Elec<R>& e, const GasDev& G, const TV& T,
   }
   const R ct = R(1) - R(2) * uC;
   const R st2 = Mr::fma(-ct, ct, R(1));
-  const R stt = st2 > R(0) ? Mr::sqrt_(st2) : R(0);
+  const R stt = st2 > R(0) ? Mr::sqrt_s(st2) : R(0);
   R sp, cp;
-  Mr::sincospi_(R(2) * uP, &sp, &cp);
-  const R vs = Mr::sqrt_(Sel<R>::two_ka(P) * es);
+  Mr::sincos2pi_s(uP, &sp, &cp);
+  const R vs = Mr::sqrt_s(Sel<R>::two_ka(P) * es);
   child.vx = vs * (stt * cp);
   child.vy = vs * (stt * sp);
   child.vz = vs * ct;
