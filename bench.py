@@ -44,7 +44,7 @@ OPS_REAL = {
     "energy loss": 3,
     "lab-frame cosine (one reciprocal square root)": 9,
     "direction normalisation (one reciprocal square root)": 13,
-    "azimuth sin/cos": 30,
+    "azimuth sin/cos (table entry, short series, addition theorem)": 25,
     "sine of the polar angle (square root)": 9,
     "rotation": 20,
     "new speed (square root) and velocity": 11,
@@ -53,7 +53,7 @@ OPS_REAL = {
 OPS_ION = {
     "two Philox blocks": 84,
     "energy split (tangent, arc tangent)": 50,
-    "two directions: sin/cos, rotation, square roots": 116,
+    "two directions: sin/cos, rotation, square roots": 106,
 }
 # the polar map and the magnetic field add, per flight: the map gather
 # (logarithm of rho^2, azimuth, bilinear weights and reads, rotation to

@@ -79,6 +79,7 @@ struct avm_gas {
   float *cum_f = nullptr, *cum0_f = nullptr, *total_f = nullptr, *band_gamma_f = nullptr,
         *band_inv_f = nullptr, *band_edge_f = nullptr;
   ChanP<float>* ch_f = nullptr;
+  double* sct = nullptr;     // azimuth table
   double* binmax = nullptr;  // per-bin maxima, kept for rebuilding the bands
   std::vector<ChanDev> host_ch;        // channel records as on the device
   std::vector<ChanP<float>> host_ch_f;
@@ -157,6 +158,7 @@ static void gas_free(avm_gas* g) {
   (void)hipFree(g->band_inv_f);
   (void)hipFree(g->band_edge_f);
   (void)hipFree(g->ch_f);
+  (void)hipFree(g->sct);
   (void)hipFree(g->binmax);
   delete g;
 }
@@ -268,7 +270,8 @@ avm_status avm_gas_create(int32_t device, double e_max_eV, int32_t n_bins, doubl
             try_hip(dmalloc(&g->cum0_f, nn), "hipMalloc") && try_hip(dmalloc(&g->total_f, nn), "hipMalloc") &&
             try_hip(dmalloc(&g->band_gamma_f, (size_t)g->n_bands), "hipMalloc") &&
             try_hip(dmalloc(&g->band_inv_f, (size_t)g->n_bands), "hipMalloc") &&
-            try_hip(dmalloc(&g->band_edge_f, (size_t)g->n_bands), "hipMalloc");
+            try_hip(dmalloc(&g->band_edge_f, (size_t)g->n_bands), "hipMalloc") &&
+            try_hip(dmalloc(&g->sct, (size_t)(2 * kAzN)), "hipMalloc");
   if (ok)
     ok = try_hip(hipMemcpyAsync(d_sig, sig.data(), sizeof(double) * sig.size(), hipMemcpyHostToDevice, st), "H2D") &&
          try_hip(hipMemcpyAsync(d_vk, vk.data(), sizeof(int32_t) * vk.size(), hipMemcpyHostToDevice, st), "H2D") &&
@@ -283,7 +286,8 @@ avm_status avm_gas_create(int32_t device, double e_max_eV, int32_t n_bins, doubl
                                   sizeof(double), nn, hipMemcpyDeviceToDevice, st), "column copy") &&
          try_hip(launch_tables_f32(g->cum, g->total, g->cum0, nn * n_channels, (int)nn, g->band_gamma,
                                    g->band_edge, g->n_bands, g->cum_f, g->total_f, g->cum0_f,
-                                   g->band_gamma_f, g->band_inv_f, g->band_edge_f, st), "FP32 tables");
+                                   g->band_gamma_f, g->band_inv_f, g->band_edge_f, st), "FP32 tables") &&
+         try_hip(launch_azimuth_table(g->sct, st), "azimuth table");
   double gamma = 0.0;
   if (ok)
     ok = try_hip(hipMemcpyAsync(&gamma, d_gamma, sizeof(double), hipMemcpyDeviceToHost, st), "D2H") &&
@@ -323,6 +327,7 @@ avm_status avm_gas_create(int32_t device, double e_max_eV, int32_t n_bins, doubl
   D.band_inv_f = g->band_inv_f;
   D.band_edge_f = g->band_edge_f;
   D.ch_f = g->ch_f;
+  D.sct = g->sct;
   float gf = (float)gamma;
   if ((double)gf < gamma) gf = std::nextafter(gf, INFINITY);  // a majorant stays a majorant
   D.gamma_f = gf;

@@ -92,6 +92,7 @@ struct GasDev {
   const float* band_inv_f;
   const float* band_edge_f;
   const ChanP<float>* ch_f;
+  const double* sct;        // [kAzN][2] sin and cos of 2 pi j / kAzN (azimuth table, FP64)
   double scale;             // n_bins / E_max
   double gamma, inv_gamma;
   double band_scale;        // n_bins / (E_max * band_bins): first guess of the band
@@ -117,6 +118,7 @@ struct TabView {
   const R* binv;
   const R* bedge;
   const ChanP<R>* ch;  // channel parameters
+  const double* sct;   // azimuth table (GasDev::sct)
 };
 
 constexpr int kLdsBands = 512;    // band tables staged in LDS (the first this many)
@@ -144,6 +146,7 @@ struct TabLds {
   const AVM_LDS R* binv;
   const AVM_LDS R* bedge;
   const AVM_LDS ChanP<R>* ch;
+  const AVM_LDS double* sct;
 };
 
 // The same LDS copies when every band and channel is staged (the persistent
@@ -160,6 +163,7 @@ struct TabFit {
   const AVM_LDS R* binv;
   const AVM_LDS R* bedge;
   const AVM_LDS ChanP<R>* ch;
+  const AVM_LDS double* sct;
 };
 
 enum FieldKind : int32_t { FIELD_SLAB = 0, FIELD_POLAR = 1 };
@@ -448,7 +452,6 @@ template <> struct M<double> {
   AVM_FN static double log_s(double x) { return log_pos(x); }
   AVM_FN static double sqrt_s(double x) { return sqrt_nn(x); }
   AVM_FN static double rsqrt_s(double x) { return rsqrt_pos(x); }
-  AVM_FN static void sincos2pi_s(double u, double* s, double* c) { sincospi_pos(u + u, s, c); }
 };
 template <> struct M<float> {
   AVM_FN static float uni(uint32_t hi, uint32_t) { return u24(hi); }
@@ -494,16 +497,44 @@ AVM_FN R dot3(R ax, R ay, R az, R bx, R by, R bz) {
 template <class R>
 AVM_FN R lerp(R a, R b, R g1, R f) { return M<R>::fma(f, b, g1 * a); }
 
+// Entries of the azimuth table: sin and cos of 2 pi j / kAzN.
+constexpr int kAzN = 256;
+
+// sin and cos of an azimuth 2 pi u, u in [0, 1].  FP64: the nearest table
+// angle 2 pi j / kAzN and the series of the remainder
+// theta = 2 pi (u - j / kAzN), |theta| <= pi / kAzN (sine to theta^7,
+// cosine to theta^6), combined by the addition theorem; the table holds
+// sincospi_pos values, so the result is within about 1.6 ulp.  (The
+// general sincospi_pos takes 19 polynomial terms.)  FP32-mixed: the
+// hardware sine and cosine of the angle in turns.
+template <class TV>
+AVM_FN void azimuth(const TV& T, double u, double* sp, double* cp) {
+  const double x = u * (double)kAzN;  // exact
+  const double jr = rint(x);
+  const double t = x - jr;            // [-1/2, 1/2], exact
+  const int j = (int)jr & (kAzN - 1);
+  const double sa = T.sct[2 * j], ca = T.sct[2 * j + 1];
+  // theta = t (2 pi / kAzN), the constant in two parts
+  const double th = __builtin_fma(t, 0x1.921fb54442d18p-6, t * 0x1.1a62633145c07p-60);
+  const double z = th * th;
+  const double sm = th * z * fma_k(__builtin_fma(z, -0x1.a01a01a01a01ap-13, 0x1.1111111111111p-7), z,
+                                   -0x1.5555555555555p-3);
+  const double cm = z * fma_k(__builtin_fma(z, -0x1.6c16c16c16c17p-10, 0x1.5555555555555p-5), z, -0.5);
+  *sp = sa + __builtin_fma(ca, th, __builtin_fma(ca, sm, sa * cm));
+  *cp = ca + __builtin_fma(-sa, th, __builtin_fma(-sa, sm, ca * cm));
+}
+template <class TV>
+AVM_FN void azimuth(const TV&, float u, float* sp, float* cp) { M<float>::sincos2pi_s(u, sp, cp); }
+
 // Direction of (dx, dy, dz) turned by polar angle theta (cos_t) and azimuth
-// phi = 2 pi u_phi (sin and cos from sincospi, no general argument
-// reduction).  The transverse length s = sqrt(dx^2 + dy^2) avoids the
+// phi = 2 pi u_phi.  The transverse length s = sqrt(dx^2 + dy^2) avoids the
 // cancellation of sqrt(1 - dz^2) next to the poles, so |d'| = 1 to rounding.
-template <class R>
-AVM_FN void turn(R dx, R dy, R dz, R cos_t, R u_phi, R& ox, R& oy, R& oz) {
+template <class R, class TV>
+AVM_FN void turn(const TV& T, R dx, R dy, R dz, R cos_t, R u_phi, R& ox, R& oy, R& oz) {
   const R st2 = M<R>::fma(-cos_t, cos_t, R(1));
   const R sin_t = st2 > R(0) ? M<R>::sqrt_s(st2) : R(0);
   R sp, cp;
-  M<R>::sincos2pi_s(u_phi, &sp, &cp);
+  azimuth(T, u_phi, &sp, &cp);
   const R q = M<R>::fma(dx, dx, dy * dy);
   const R tiny = sizeof(R) == 8 ? R(1e-24) : R(1e-12);
   if (q > tiny) {
@@ -723,11 +754,11 @@ template <> struct Sel<float> {
 // The global-memory tables of precision R (no LDS copies).
 template <class R> AVM_FN TabView<R> global_view(const GasDev& G);
 template <> AVM_FN TabView<double> global_view<double>(const GasDev& G) {
-  return TabView<double>{G.total, G.cum0, G.n_bins + 1, G.band_gamma, G.band_inv, G.band_edge, G.ch};
+  return TabView<double>{G.total, G.cum0, G.n_bins + 1, G.band_gamma, G.band_inv, G.band_edge, G.ch, G.sct};
 }
 template <> AVM_FN TabView<float> global_view<float>(const GasDev& G) {
   return TabView<float>{G.total_f, G.cum0_f, G.n_bins + 1, G.band_gamma_f, G.band_inv_f,
-                        G.band_edge_f, G.ch_f};
+                        G.band_edge_f, G.ch_f, G.sct};
 }
 
 // Band tables and channel parameters through either view.  Beyond the LDS
@@ -1002,8 +1033,8 @@ AVM_FN R band_crossing(const RunParams& P, const Elec<R>& e, R ax, R ay, R az, R
 // New velocity after a real collision: the old direction turned by
 // (cos_t, phi = 2 pi uB), speed from the new energy.  (The caller advances
 // the flight index.)
-template <class R>
-AVM_FN void scatter_to(Elec<R>& e, const RunParams& P, R cos_t, R uB, R e_new) {
+template <class R, class TV>
+AVM_FN void scatter_to(Elec<R>& e, const RunParams& P, const TV& T, R cos_t, R uB, R e_new) {
   const R v2 = dot3<R>(e.vx, e.vy, e.vz, e.vx, e.vy, e.vz);
   R dx = R(0), dy = R(0), dz = R(1);
   if (v2 > R(0)) {
@@ -1013,7 +1044,7 @@ AVM_FN void scatter_to(Elec<R>& e, const RunParams& P, R cos_t, R uB, R e_new) {
     dz = e.vz * inv;
   }
   R ox, oy, oz;
-  turn<R>(dx, dy, dz, cos_t, uB, ox, oy, oz);
+  turn<R>(T, dx, dy, dz, cos_t, uB, ox, oy, oz);
   const R sp1 = M<R>::sqrt_s(Sel<R>::two_ka(P) * e_new);
   e.vx = sp1 * ox;
   e.vy = sp1 * oy;
@@ -1315,7 +1346,7 @@ AVM_FN int32_t flight_step(Elec<R>& e, const GasDev& G, const TV& T, const Field
               cos_t = R(1) - R(2) * uA;
             }
             if (ret == STEP_CONTINUE) {
-              scatter_to<R>(e, P, cos_t, uB, e_new);
+              scatter_to<R>(e, P, T, cos_t, uB, e_new);
               e_band = e_new;
             }
           }
@@ -1434,7 +1465,7 @@ AVM_FN void complete_ionisation(Elec<R>& e, const GasDev& G, const TV& T,
   const R st2 = Mr::fma(-ct, ct, R(1));
   const R stt = st2 > R(0) ? Mr::sqrt_s(st2) : R(0);
   R sp, cp;
-  Mr::sincos2pi_s(uP, &sp, &cp);
+  azimuth(T, uP, &sp, &cp);
   const R vs = Mr::sqrt_s(Sel<R>::two_ka(P) * es);
   child.vx = vs * (stt * cp);
   child.vy = vs * (stt * sp);
@@ -1442,7 +1473,7 @@ AVM_FN void complete_ionisation(Elec<R>& e, const GasDev& G, const TV& T,
   child.e = es;
   child.eid = (((uint64_t)w3.w3 << 32) | (uint64_t)w3.w2) & 0x7FFFFFFFFFFFFFFFull;
   e.n_ion += 1;
-  scatter_to<R>(e, P, R(1) - R(2) * uA, uB, e_new);
+  scatter_to<R>(e, P, T, R(1) - R(2) * uA, uB, e_new);
   e.k += 1;
   if (kBanded) e.band = band_of<R>(G, T, e_new);
 }

@@ -116,6 +116,7 @@ hipError_t launch_zero(double* p, size_t n, hipStream_t st);
 int persistent_block();  // threads per block of the persistent kernel
 hipError_t persistent_occupancy(int fp32, int banded, int field_kind, int signal, int fit, int block,
                                 int* blocks_per_cu);
+hipError_t launch_azimuth_table(double* sct, hipStream_t st);
 hipError_t launch_tables_f32(const double* cum, const double* total, const double* cum0,
                              size_t n_cum, int n_nodes, const double* bg, const double* be,
                              int n_bands, float* cum_f, float* total_f, float* cum0_f, float* bg_f,

@@ -574,6 +574,7 @@ __global__ void __launch_bounds__(kPBlock)
   __shared__ R s_tot[kLdsNodes], s_cum0[kLdsNodes];
   __shared__ R s_bg[kLdsBands], s_bi[kLdsBands], s_be[kLdsBands];
   __shared__ ChanP<R> s_ch[kLdsChannels];
+  __shared__ double s_sct[2 * kAzN];
   __shared__ unsigned long long s_tally[kTally];
   __shared__ WaveAcc wacc_all[kPBlock / 64];
   if (threadIdx.x < kTally) s_tally[threadIdx.x] = 0;
@@ -595,10 +596,12 @@ __global__ void __launch_bounds__(kPBlock)
   }
   const int n_lc = G.n_ch < kLdsChannels ? G.n_ch : kLdsChannels;
   if ((int)threadIdx.x < n_lc) s_ch[threadIdx.x] = Tg.ch[threadIdx.x];
+  for (int k = threadIdx.x; k < 2 * kAzN; k += kPBlock) s_sct[k] = G.sct[k];
   __syncthreads();
   using View = std::conditional_t<kFit, TabFit<R>, TabLds<R>>;
   const View T{(const AVM_LDS R*)s_tot, (const AVM_LDS R*)s_cum0, n_lo, (const AVM_LDS R*)s_bg,
-               (const AVM_LDS R*)s_bi, (const AVM_LDS R*)s_be, (const AVM_LDS ChanP<R>*)s_ch};
+               (const AVM_LDS R*)s_bi, (const AVM_LDS R*)s_be, (const AVM_LDS ChanP<R>*)s_ch,
+               (const AVM_LDS double*)s_sct};
   Xfer& X = xfer_all[threadIdx.x >> 6];
   const uint32_t lane = __lane_id();
   bool has = false, cp = false;
@@ -947,6 +950,23 @@ __global__ void k_tables_f32(const double* __restrict__ cum, const double* __res
     bi_f[i] = 1.0f / g;
     be_f[i] = __double2float_rd(be[i]);
   }
+}
+
+// The azimuth table: sin and cos of 2 pi j / kAzN, j = 0 .. kAzN - 1, from
+// sincospi_pos at the exact argument j / (kAzN / 2).
+__global__ void k_azimuth_table(double* __restrict__ sct) {
+  const int j = (int)threadIdx.x;
+  if (j < kAzN) {
+    double sn, cs;
+    sincospi_pos((double)j / (double)(kAzN / 2), &sn, &cs);
+    sct[2 * j] = sn;
+    sct[2 * j + 1] = cs;
+  }
+}
+
+hipError_t launch_azimuth_table(double* sct, hipStream_t st) {
+  hipLaunchKernelGGL(k_azimuth_table, dim3(1), dim3(kAzN), 0, st, sct);
+  return hipGetLastError();
 }
 
 hipError_t launch_tables_f32(const double* cum, const double* total, const double* cum0,
