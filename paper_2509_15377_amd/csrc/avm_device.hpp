@@ -818,6 +818,35 @@ AVM_FN int32_t band_of(const GasDev& G, const TV& T, R e) {
   return b;
 }
 
+// band_of() that also hands back the band's majorant, its inverse and its
+// upper edge: read together with the edges of the first guess, so a flight
+// whose lookahead lands in the guessed band waits for one LDS round trip.
+template <class R, class TV>
+AVM_FN int32_t band_of_tabs(const GasDev& G, const TV& T, R e, R& gam, R& inv, R& edge) {
+  const int32_t nb = G.n_bands;
+  int32_t b = (int32_t)(e * Sel<R>::band_scale(G));
+  b = b < 0 ? 0 : (b > nb - 1 ? nb - 1 : b);
+  const int32_t guess = b;
+  const R hi = band_edge(G, T, b);
+  const R lo = band_edge(G, T, b > 0 ? b - 1 : 0);
+  gam = band_gamma(G, T, b);
+  inv = band_inv(G, T, b);
+  edge = hi;
+  if (b < nb - 1 && !(e < hi)) {
+    ++b;
+    while (b < nb - 1 && !(e < band_edge(G, T, b))) ++b;
+  } else if (b > 0 && e < lo) {
+    --b;
+    while (b > 0 && e < band_edge(G, T, b - 1)) --b;
+  }
+  if (b != guess) {
+    gam = band_gamma(G, T, b);
+    inv = band_inv(G, T, b);
+    edge = band_edge(G, T, b);
+  }
+  return b;
+}
+
 // Termination status of a position outside the drift region, 0 inside
 // (the geometry is the kernel's kField, the same as F.kind).
 template <class R, int kField>
@@ -1194,7 +1223,10 @@ AVM_FN int32_t flight_step(Elec<R>& e, const GasDev& G, const TV& T, const Field
   const int32_t band0 = e.band;
   const R gam0 = kBanded ? band_gamma(G, T, band0) : Sel<R>::gamma(G);
   const R inv0 = kBanded ? band_inv(G, T, band0) : Sel<R>::inv_gamma(G);
+  const R edge0 = kBanded ? band_edge(G, T, band0) : R(0);
   const R nlog = -Mr::log_s(u1);
+  // the flight's band: its majorant, inverse and upper edge
+  R gam = gam0, inv_gam = inv0, edge = edge0;
   if (kBanded && P.look > 0.0 && e.band < G.n_bands - 1) {
     // lookahead: raise the band to the band of the energy after `look` mean
     // free times of the current band (the flight energy, or its helical
@@ -1211,16 +1243,23 @@ AVM_FN int32_t flight_step(Elec<R>& e, const GasDev& G, const TV& T, const Field
       const R fx = Mr::fma(ax, sl, e.vx), fy = Mr::fma(ay, sl, e.vy), fz = Mr::fma(az, sl, e.vz);
       e_look = dot3<R>(fx, fy, fz, fx, fy, fz) * Sel<R>::inv_2ka(P);
     }
-    const int32_t bl = band_of<R>(G, T, e_look);
-    if (bl > e.band) e.band = bl;
+    R gl, il, el;
+    const int32_t bl = band_of_tabs<R>(G, T, e_look, gl, il, el);
+    if (bl > e.band) {
+      e.band = bl;
+      gam = gl;
+      inv_gam = il;
+      edge = el;
+    }
   }
-  if (helical)
+  if (helical) {
+    const int32_t b1 = e.band;
     while (e.band < G.n_bands - 1 && (hb.vp * hb.vp + hb.p * hb.p) * P.inv_2ka >= (double)band_edge(G, T, e.band))
       e.band += 1;
-  R gam = gam0, inv_gam = inv0;
-  if (kBanded && e.band != band0) {
-    gam = band_gamma(G, T, e.band);
-    inv_gam = band_inv(G, T, e.band);
+    if (e.band != b1) {
+      gam = band_gamma(G, T, e.band);
+      inv_gam = band_inv(G, T, e.band);
+    }
   }
   const R tau = nlog * inv_gam;
   R tau_end = tau;
@@ -1236,7 +1275,6 @@ AVM_FN int32_t flight_step(Elec<R>& e, const GasDev& G, const TV& T, const Field
     }
   } else if (kBanded && e.band < G.n_bands - 1) {
     const R fx = Mr::fma(ax, tau, e.vx), fy = Mr::fma(ay, tau, e.vy), fz = Mr::fma(az, tau, e.vz);
-    const R edge = band_edge(G, T, e.band);
     if (dot3<R>(fx, fy, fz, fx, fy, fz) * Sel<R>::inv_2ka(P) >= edge) {
       const R tc = band_crossing<R>(P, e, ax, ay, az, edge);
       if (tc < tau_end) {
