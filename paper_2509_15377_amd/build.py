@@ -22,6 +22,9 @@ SOURCES = ["avm_kernels.hip", "avm_api.cpp", "avm_noalloc.hip"]
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
     "-mllvm", "-disable-machine-licm",
+    # the iterative occupancy-first scheduler: the same registers, ~1 % faster
+    # transport kernels than the default scheduler (same results)
+    "-mllvm", "-amdgpu-sched-strategy=iterative-maxocc",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function",
 ]
