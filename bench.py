@@ -87,12 +87,11 @@ CAPACITY = {"toy": 2_000_000, "argon": 16_000_000, "batched": 200_000_000,
 
 # HBM traffic of the transport kernel from two counter passes (FETCH_SIZE,
 # WRITE_SIZE per dispatch), valid only for the kernel sources, launch
-# settings and compiler flags it was taken on.
+# defaults (avm_internal.hpp) and compiler flags it was taken on.
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_persistent_argon1000_fp64_banded.json")
 KERNEL_SOURCES = ("paper_2509_15377_amd/csrc/avm_kernels.hip",
                   "paper_2509_15377_amd/csrc/avm_device.hpp",
                   "paper_2509_15377_amd/csrc/avm_internal.hpp",
-                  "paper_2509_15377_amd/csrc/avm_api.cpp",
                   "paper_2509_15377_amd/build.py")
 
 

@@ -20,12 +20,6 @@
 
 using namespace avm;
 
-// Flights a lane makes between two visits of its wave to the queue when the
-// caller leaves it at 0 (same-box sweeps of 32 to 44 on the slab workloads:
-// 40 is 1.6-1.8 % faster than 32 in FP64 and 4 % in FP32-mixed; the wire
-// chamber is flat between 24 and 44).
-constexpr int32_t kDefaultFlightsPerPass = 40;
-
 namespace {
 
 thread_local std::string g_err;
@@ -1225,7 +1219,7 @@ hipError_t tune_key(const avm_gas* g, const avm_field* fl, const avm_primary* pr
 // Version of the cache lines: raised whenever the transport kernel changes
 // enough that an earlier timing no longer ranks the candidates right, so
 // that lines from an older library are ignored (and a new choice appended).
-constexpr int kTuneLineVersion = 4;
+constexpr int kTuneLineVersion = 5;
 
 bool cache_lookup(const char* path, uint64_t key, int* fpp, int* wpc, int* bb, float* look, double* ms) {
   if (!path) return false;
@@ -1336,7 +1330,7 @@ extern "C" avm_status avm_autotune(avm_gas* gas, const avm_field* field, const a
     *ms = best;
     return AVM_OK;
   };
-  const int fpps[] = {8, 16, 32, 64, 128};
+  const int fpps[] = {8, 16, 24, 32, 40, 48, 64, 128};
   std::vector<int> bands = {bb0};
   if (tune_bands)
     for (int b : {25, 50, 100, 200, 400})
@@ -1364,7 +1358,7 @@ extern "C" avm_status avm_autotune(avm_gas* gas, const avm_field* field, const a
   for (float l : looks) consider(best.fpp, best.wpc, best.bb, l);
   for (int b : bands) consider(best.fpp, best.wpc, b, best.look);
   const int f0 = best.fpp;
-  for (int f : {f0 / 2, f0 * 2})
+  for (int f : {f0 - 4, f0 + 4})
     if (f >= 4 && f <= 256) consider(f, best.wpc, best.bb, best.look);
   for (int w : wpcs) consider(best.fpp, w, best.bb, best.look);
   avm_run_destroy(r);
