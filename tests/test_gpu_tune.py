@@ -77,7 +77,8 @@ def test_autotune_choice_and_cache(A, oracle_mod, tmp_path):
     assert res["trials"] >= 8 and res["from_cache"] == 0
     assert res["best_ms"] <= res["start_ms"]
     assert g.band_bins == res["band_bins"]
-    assert cache.read_text().count("avm_tune 4 ") == 1
+    lines = [ln.split() for ln in cache.read_text().splitlines()]
+    assert len(lines) == 1 and lines[0][0] == "avm_tune" and lines[0][2] == "%016x" % res["key"]
     # launch parameters do not change results: tuned == default at that band width
     look = res["band_lookahead"]
     tuned = A.Run(g, f, wl.primaries, wl.n_aval, flights_per_pass=res["flights_per_pass"],
