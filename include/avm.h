@@ -189,7 +189,7 @@ typedef struct {
   int32_t precision;      /* avm_precision                                               */
   int32_t majorant;       /* avm_majorant (banded needs B = 0 and band_bins > 0)          */
   int32_t mode;           /* avm_mode                                                    */
-  int32_t flights_per_pass; /* batched: flights between queue visits (0: 40)              */
+  int32_t flights_per_pass; /* batched: flights between queue visits (0: 40 FP64, 48 FP32) */
   double t_max_ns;        /* time limit (INFINITY: none) -> status 6                     */
   uint64_t capacity;      /* electrons the run can hold (primaries included), >= n_prim  */
   uint32_t k_max;         /* flights per electron before status 7; 0: 2^30-1             */

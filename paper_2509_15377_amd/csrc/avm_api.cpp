@@ -656,7 +656,7 @@ static avm_status check_opts(const char* fn, const avm_gas* gas, const avm_field
   if (std::isnan(o.t_max_ns)) return fail(AVM_E_ARG, "%s: t_max is NaN", fn);
   if (o.capacity < n_prim) return fail(AVM_E_ARG, "%s: capacity %llu < %llu primaries", fn, (unsigned long long)o.capacity, (unsigned long long)n_prim);
   if (o.capacity > 0xFFFFFFF0ull) return fail(AVM_E_ARG, "%s: capacity above 2^32-16", fn);
-  if (o.flights_per_pass <= 0) o.flights_per_pass = kDefaultFlightsPerPass;
+  if (o.flights_per_pass <= 0) o.flights_per_pass = default_flights_per_pass(o.precision);
   if (o.waves_per_cu < 0) return fail(AVM_E_ARG, "%s: waves_per_cu < 0", fn);
   if (!(o.band_lookahead >= 0.0f) || !std::isfinite(o.band_lookahead))
     return fail(AVM_E_ARG, "%s: band_lookahead must be finite and >= 0", fn);
@@ -1256,7 +1256,7 @@ extern "C" avm_status avm_autotune(avm_gas* gas, const avm_field* field, const a
   std::memset(out, 0, sizeof *out);
   avm_run_opts o = *base;
   o.graph = 0;
-  if (o.flights_per_pass <= 0) o.flights_per_pass = kDefaultFlightsPerPass;  // the run's default
+  if (o.flights_per_pass <= 0) o.flights_per_pass = default_flights_per_pass(o.precision);  // as a run
   const bool tune_bands = (flags & AVM_TUNE_BANDS) && o.majorant == AVM_MAJORANT_BANDED && !field->dev.has_b;
   const int32_t bb0 = gas->band_bins;
   DeviceGuard dg(gas->device);

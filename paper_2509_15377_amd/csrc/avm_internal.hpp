@@ -13,10 +13,15 @@ namespace avm {
 static_assert(sizeof(avm_end_record) == 72 && alignof(avm_end_record) == 8, "end record layout");
 
 // Flights a lane makes between two visits of its wave to the queue when the
-// caller leaves it at 0 (same-box sweeps of 32 to 44 on the slab workloads:
-// 40 is 1.6-1.8 % faster than 32 in FP64 and 4 % in FP32-mixed; the wire
-// chamber is flat between 24 and 44).
+// caller leaves it at 0, by precision.  Same-box sweeps on the slab
+// workloads: in FP64, 40 is 1.6-1.8 % faster than 32 (44 no better); in
+// FP32-mixed, whose flight steps are shorter, 48 is 1-2.6 % faster than 40
+// (56 no better).  The wire chamber is flat from 24 to 48 in both.
 constexpr int32_t kDefaultFlightsPerPass = 40;
+constexpr int32_t kDefaultFlightsPerPassF32 = 48;
+inline int32_t default_flights_per_pass(int32_t precision) {
+  return precision == AVM_FP32_MIXED ? kDefaultFlightsPerPassF32 : kDefaultFlightsPerPass;
+}
 
 // Per-avalanche statistics (and totals, with the status histogram).
 struct AvalStats {
