@@ -27,7 +27,11 @@ def test_penning_against_oracle(A, oracle_mod, majorant):
     ref = oracle_mod.run(og, wl.field, wl.primaries, wl.seed, banded=banded)
     ep, tot, per = A.run(wl, band_bins=100, majorant=A.BANDED if banded else A.GLOBAL,
                          capacity=8_000_000, timeout_s=60.0)
-    rep = CMP.assert_parity(ep, ref)
+    # with the global majorant every electron makes tens of thousands of null
+    # flights, and rounding drift past 1e-9 with identical decisions shares
+    # the 0.1 % budget of rounding-induced deviations with the flips, as in
+    # the argon-like gas's global-majorant parity test
+    rep = CMP.assert_parity(ep, ref, max_drift_fraction=1e-4 if banded else 1e-3)
     assert np.array_equal(per["n_endpoints"], 1 + per["n_ion"])
     energies = {round(c.penning_energy_eV, 9) for c in wl.gas.channels if c.penning_prob > 0}
     n_transfer = sum(round(float(x), 9) in energies for x in ep["e0"][ep["parent"] != 0])
