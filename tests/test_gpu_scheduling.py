@@ -22,16 +22,19 @@ def _sorted(ep):
     return ep[np.lexsort((ep["eid"], ep["aval"]))]
 
 
-def test_pass_length_does_not_change_results(A):
-    """One flight per pass (an exchange after every flight), an odd length
-    and a long one give the same bits as the default on 40 argon
-    avalanches, banded with lookahead."""
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_pass_length_does_not_change_results(A, precision):
+    """One flight per pass (an exchange after every flight), an odd length,
+    the other precision's default and a long one give the same bits as the
+    default (40 flights in FP64, 48 in FP32-mixed) on 40 argon avalanches,
+    banded with lookahead."""
     wl = W.argon(40)
     g = A.Gas(wl.gas, band_bins=100)
     f = A.Field(wl.field)
-    kw = dict(seed=wl.seed, majorant=A.BANDED, band_lookahead=1.0, capacity=4_000_000, timeout_s=60.0)
+    kw = dict(seed=wl.seed, majorant=A.BANDED, band_lookahead=1.0, capacity=4_000_000, timeout_s=60.0,
+              precision=A.FP64 if precision == "fp64" else A.FP32_MIXED)
     ref = None
-    for fpp in (0, 1, 7, 100):
+    for fpp in (0, 1, 7, 40, 48, 100):
         r = A.Run(g, f, wl.primaries, wl.n_aval, flights_per_pass=fpp, **kw)
         r.execute()
         r.sync()
@@ -43,7 +46,7 @@ def test_pass_length_does_not_change_results(A):
             ref = ep
         else:
             assert ep.tobytes() == ref.tobytes(), fpp
-    print("pass lengths 1, 7, 100 and default agree on", ref.size, "electrons")
+    print(precision, "pass lengths 1, 7, 40, 48, 100 and the default agree on", ref.size, "electrons")
 
 
 @pytest.mark.parametrize("graph", [False, True])
